@@ -1,0 +1,273 @@
+"""Benchmark of the MI355X aggregation scan (one JSON line on stdout).
+
+Workload: one column each of 2^30 int32, int64 and float32 items (uniform,
+seeded), resident in HBM; one step runs SUM, MIN, MAX, COUNT and AVG on each
+column through agg_run (float SUM / AVG in the default compensated mode).
+`value` is the step's algorithmic bytes (every item read once per function that
+reads items; COUNT reads none) divided by the step time.
+
+Also reported, outside the timed steps: the per-cell GB/s and roofline
+fraction, the dominant kernel's roofline (HIP events over the timed region),
+the plain and f64-combine float modes, the 2^20-item int32 SUM latency, the
+end-to-end rate from pinned host memory (chunked copy pipeline and zero-copy)
+with the measured host-to-device copy ceiling, and the CPU oracle's rate on
+one step's worth of the same cells (cpu_baseline).
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+PCIE_PEAK_GBS = 64.0           # PCIe Gen5 x16, one direction, nominal
+METRIC = "aggregation GB/s and % of HBM peak (on-device + end-to-end), 1 MI355X"
+N_ITEMS = 1 << 30
+DTYPES = ["i32", "i64", "f32"]
+OPS = ["sum", "min", "max", "count", "avg"]
+WIDTH = {"i32": 4, "i64": 8, "f32": 4}
+SEEDS = {"i32": 2, "i64": 3, "f32": 4}
+KERNEL_SOURCES = ["paper_2606_10030_amd/csrc/agg_device.hpp", "paper_2606_10030_amd/csrc/agg_kernels.hip"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, n_bytes_alg: int):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-e2e", action="store_true")
+    ap.add_argument("--n", type=int, default=N_ITEMS, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the scan's only cross-GPU step would be a 32-byte partial exchange)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import datagen
+    import paper_2606_10030_amd as agg
+
+    torch.cuda.set_device(0)
+    info = agg.device_info(0)
+    n = args.n
+    stream = torch.cuda.current_stream()
+
+    # ---- inputs: generated into pinned host memory, copied to HBM
+    host, dev = {}, {}
+    for dt in DTYPES:
+        t0 = time.time()
+        tdt = {"i32": torch.int32, "i64": torch.int64, "f32": torch.float32}[dt]
+        h = torch.empty(n, dtype=tdt, pin_memory=True)
+        datagen.fill_ptr(h.data_ptr(), n, dt, "uniform", SEEDS[dt])
+        host[dt] = h
+        dev[dt] = h.to("cuda", non_blocking=False)
+        log(f"input {dt}: {n} items generated and copied in {time.time() - t0:.1f}s")
+    torch.cuda.synchronize()
+
+    plans = {(dt, op): agg.Plan(dt, op, max_n=n) for dt in DTYPES for op in OPS}
+    outs = torch.zeros(len(plans) * 32, dtype=torch.uint8, device="cuda")
+    cells = list(plans.keys())
+
+    def step(ev=None):
+        for i, (dt, op) in enumerate(cells):
+            if ev is not None:
+                ev[i][0].record(stream)
+            plans[(dt, op)].enqueue(dev[dt], outs[i * 32:(i + 1) * 32], stream=stream)
+            if ev is not None:
+                ev[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---- timed region
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cells]
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        step(ev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+
+    cell_ms = {c: [ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(args.steps)] for i, c in enumerate(cells)}
+    bytes_of = {c: (0 if c[1] == "count" else n * WIDTH[c[0]]) for c in cells}
+    step_bytes = sum(bytes_of.values())
+    ms_per_step = wall * 1e3 / args.steps
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+
+    table = {}
+    for c in cells:
+        m = statistics.mean(cell_ms[c])
+        gbs = bytes_of[c] / (m * 1e-3) / 1e9 if bytes_of[c] else None
+        table[f"{c[0]}_{c[1]}"] = {"ms": round(m, 4), "GB/s": None if gbs is None else round(gbs, 1),
+                                   "rows/s": round(n / (m * 1e-3), 1),
+                                   "hbm_frac": None if gbs is None else round(gbs / HBM_PEAK_GBS, 4)}
+
+    # dominant kernel: the kernel with the largest total time per step (SUM and AVG share one)
+    kernel_of = {}
+    for dt, op in cells:
+        if op == "count":
+            continue
+        k = f"{dt}_{'sum' if op in ('sum', 'avg') else op}"
+        kernel_of.setdefault(k, []).append((dt, op))
+    tot = {k: sum(statistics.mean(cell_ms[c]) for c in cs) for k, cs in kernel_of.items()}
+    dom = max(tot, key=tot.get)
+    dom_cells = kernel_of[dom]
+    dom_ms = statistics.mean([x for c in dom_cells for x in cell_ms[c]])
+    dom_bytes = n * WIDTH[dom_cells[0][0]]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom, dom_bytes),
+                "kernel": f"scan {dom} (agg_run: one launch per call)",
+                "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_ms, 4),
+                "launches_timed": len(dom_cells) * args.steps}
+
+    extra = {}
+    # ---- float precision modes (same column, untimed-step measurement)
+    modes = {}
+    for prec in ("neumaier", "f64_combine", "f32"):
+        p = agg.Plan("f32", "sum", max_n=n, prec=prec)
+        o = torch.zeros(32, dtype=torch.uint8, device="cuda")
+        for _ in range(2):
+            p.enqueue(dev["f32"], o, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            p.enqueue(dev["f32"], o, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        modes[prec] = {"ms": round(ms, 4), "GB/s": round(n * 4 / (ms * 1e-3) / 1e9, 1)}
+        p.close()
+    extra["f32_sum_modes"] = modes
+
+    # ---- latency: 2^20 int32 SUM (launch-bound)
+    small = dev["i32"][: 1 << 20]
+    p = agg.Plan("i32", "sum", max_n=1 << 20)
+    o = torch.zeros(32, dtype=torch.uint8, device="cuda")
+    for _ in range(20):
+        p.enqueue(small, o, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(200):
+        p.enqueue(small, o, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    extra["i32_sum_2e20_us_per_call"] = round(e0.elapsed_time(e1) / 200 * 1e3, 2)
+    p.close()
+
+    # ---- end to end from pinned host memory
+    if not args.no_e2e:
+        e2e = {}
+        dst = torch.empty_like(dev["i32"])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dst.copy_(host["i32"], non_blocking=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        h2d = n * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        e2e["h2d_copy_GB/s"] = round(h2d, 2)
+        del dst
+        for src in ("pinned_host", "zerocopy"):
+            for dt in DTYPES:
+                p = agg.Plan(dt, "sum", max_n=n, src=src)
+                p.enqueue(host[dt][: 1 << 24], o, n=1 << 24, stream=stream)  # warm the path
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                t0 = time.perf_counter()
+                e0.record(stream)
+                p.enqueue(host[dt], o, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                wall_s = time.perf_counter() - t0
+                gbs = n * WIDTH[dt] / (e0.elapsed_time(e1) * 1e-3) / 1e9
+                e2e[f"{src}_{dt}_sum"] = {"GB/s": round(gbs, 2), "pcie_frac": round(gbs / PCIE_PEAK_GBS, 3),
+                                          "h2d_ceiling_frac": round(gbs / h2d, 3),
+                                          "wall_ms": round(wall_s * 1e3, 2)}
+                p.close()
+        dev_ms = statistics.mean(cell_ms[("i32", "sum")])
+        e2e_ms = n * 4 / (e2e["pinned_host_i32_sum"]["GB/s"] * 1e9) * 1e3
+        e2e["transfer_share_of_e2e_time"] = round(1 - dev_ms / e2e_ms, 4)
+        extra["e2e"] = e2e
+
+    # ---- CPU oracle baseline (rank 0, N = 1): one step's cells on the host cores
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.default_threads()
+        cells_cpu = [c for c in cells if c[1] != "count"]
+        t0 = time.perf_counter()
+        for dt, op in cells_cpu:
+            oracle.aggregate_ptr(host[dt].data_ptr(), n, {"i32": 0, "i64": 1, "f32": 2}[dt],
+                                 {"sum": 0, "min": 1, "max": 2, "avg": 4}[op], threads)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": round(step_bytes / cpu_s / 1e9, 2), "unit": "GB/s", "cores": threads, "kind": "oracle",
+               "sample": f"one full step: {len(cells_cpu)} cells over the same 2^30-item columns "
+                         f"({step_bytes / 2**30:.0f} GiB read), {cpu_s:.1f} s"}
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64,f32",
+        "data": "synthetic",
+        "config": {"workload": "aggregation scan of 2^30-item int32, int64 and float32 columns "
+                               "(uniform), SUM/MIN/MAX/COUNT/AVG, resident in HBM",
+                   "n": n, "bytes_per_step": step_bytes, "parallelism": "single GPU",
+                   "device": info},
+        "hbm_frac": round(value / HBM_PEAK_GBS, 4),
+        "rows_per_s": round(n * len(cells) / (ms_per_step * 1e-3), 1),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "cells": table,
+        **extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

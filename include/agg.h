@@ -1,0 +1,225 @@
+/*
+ * agg.h -- C ABI of libagg.so, the MI355X (gfx950) in-memory aggregation scan.
+ *
+ * The operation (paper Section 2.1 with the kernel of Figure 4; Section 3.2
+ * for the specialised GPU form): read every item x[0..n) of one column and
+ * fold it with an aggregation function into one summary value,
+ * r = aggregate(r, x[i]) for all i.  Functions: SUM, MIN, MAX, COUNT, AVG.
+ * Columns are dense, non-nullable arrays of int32, int64 or float32.
+ *
+ * Results:
+ *   integer SUM     two's-complement sum mod 2^64 of the items widened to
+ *                   int64 (exact, bit-identical to any evaluation order);
+ *   integer MIN/MAX the extreme item, widened to int64;
+ *   COUNT           n;
+ *   integer AVG     RN(RN(SUM) / RN(n)) in IEEE double;
+ *   float SUM/AVG   an approximation of the exact sum (see agg_prec) held in
+ *                   a double; AVG divides it by RN(n);
+ *   float MIN/MAX   the extreme item (NaN items skipped), widened to double.
+ * Empty column: SUM = 0 and COUNT = 0; MIN, MAX and AVG report is_null = 1.
+ *
+ * Determinism: for a given (dtype, op, prec, n) the library always uses one
+ * canonical reduction shape (agg_canonical_shape).  The result bits depend
+ * only on the column's contents and that shape -- not on the tuning
+ * parameters, the grid, the source (device / pinned host / zero-copy), or
+ * whether the column runs alone (agg_run) or inside a batch (agg_batch_run).
+ *
+ * Conventions:
+ *   - Every function returns AGG_OK (0) or a negative AGG_E_* code and never
+ *     aborts; after AGG_E_HIP, agg_last_hip_error() gives the hipError_t.
+ *   - Pointers are plain addresses.  The caller owns columns and result
+ *     buffers; plans and batches own their workspaces (allocated at creation,
+ *     freed by the destroy call), so agg_run and agg_batch_run allocate
+ *     nothing.
+ *   - Work is asynchronous on the caller's HIP stream (`stream` is a
+ *     hipStream_t; NULL = the legacy default stream).  A result is valid once
+ *     that stream has been synchronised.
+ *   - A plan or batch is not re-entrant: two calls that overlap in time (for
+ *     instance on two streams) must use two plans.
+ */
+#ifndef AGG_H
+#define AGG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define AGG_OK 0
+#define AGG_E_INVALID (-1)     /* bad argument: null pointer, n < 0, n > max_n,
+                                  bad enum, misaligned or non-device pointer */
+#define AGG_E_NOMEM (-2)       /* a workspace allocation failed */
+#define AGG_E_NODEVICE (-3)    /* no HIP device, or not a gfx950 device */
+#define AGG_E_HIP (-4)         /* a HIP runtime call failed */
+
+/* ---- enums (passed as int32_t) ---- */
+enum { AGG_I32 = 0, AGG_I64 = 1, AGG_F32 = 2 };
+enum { AGG_SUM = 0, AGG_MIN = 1, AGG_MAX = 2, AGG_COUNT = 3, AGG_AVG = 4 };
+/* Float SUM / AVG precision modes (ignored for other dtype/op pairs):
+ *   NEUMAIER     per-lane Neumaier-compensated float32 (sum, correction)
+ *                pairs, combined across lanes by exact two-sum; each segment
+ *                partial is sum + correction in double; double combine.
+ *   F32          plain float32 everywhere, including the final combine.
+ *   F64_COMBINE  plain float32 lanes and wave reduction, segment partials
+ *                widened to double, double combine. */
+enum { AGG_PREC_NEUMAIER = 0, AGG_PREC_F32 = 1, AGG_PREC_F64_COMBINE = 2 };
+/* Where the column lives:
+ *   DEVICE       device memory (HBM), the on-device scan;
+ *   PINNED_HOST  page-locked host memory, staged to HBM in chunks on a copy
+ *                stream that overlaps the scan (end to end, Section 5.3);
+ *   ZEROCOPY     page-locked host memory read directly by the kernel over
+ *                PCIe. */
+enum { AGG_SRC_DEVICE = 0, AGG_SRC_PINNED_HOST = 1, AGG_SRC_ZEROCOPY = 2 };
+
+/* ---- records ---- */
+typedef struct agg_result {   /* 32 bytes */
+    int64_t i64;      /* integer SUM / MIN / MAX, COUNT; integer AVG: the SUM */
+    double f64;       /* float results, AVG; integer results converted */
+    int64_t count;    /* n */
+    int32_t is_null;  /* 1: MIN / MAX / AVG of an empty column */
+    int32_t prec_used;/* agg_prec for float SUM / AVG, else -1 */
+} agg_result;
+
+/* Launch parameters.  None of them changes a result bit. */
+typedef struct agg_tune {
+    int32_t waves_per_block;  /* 1, 2, 4, 8 or 16 (block = 64 * waves_per_block threads) */
+    int32_t blocks_per_cu;    /* 1..32; grid = blocks_per_cu * CU count,
+                                 capped by the work available */
+    int32_t unroll;           /* 4, 8, 16 or 32 outstanding 16-byte loads per lane */
+    int32_t nontemporal;      /* 1: streaming (non-temporal) loads */
+    int64_t chunk_bytes;      /* PINNED_HOST: bytes per staged chunk */
+    int32_t staging_depth;    /* PINNED_HOST: chunks in flight, 2..4 */
+    int32_t reserved;
+} agg_tune;
+
+/* The canonical reduction shape of a column.  The column's bytes are cut
+ * into nseg contiguous segments of seg_bytes (the last one may be short).
+ * Segment j is folded by one wave: lane l reads the 16-byte vectors at
+ * byte offsets j*seg_bytes + r*1024 + 16*l for r = 0, 1, ..., each vector
+ * component into its own accumulator in order of r; the components are
+ * merged as (c0 + c1) + (c2 + c3) (int64 / f32 with 4 per vector) or c0 + c1;
+ * the 64 lanes are merged by a fixed butterfly (xor 1, 2; mirrors in 8 and
+ * 16 lanes; row pairs; halves).  The nseg segment partials are folded by 256
+ * lanes, lane L taking partials L, L + 256, ... in order, then the same
+ * butterfly, then the four wave totals as (w0 + w1) + (w2 + w3). */
+typedef struct agg_shape {
+    int64_t seg_bytes;     /* power of two, >= 16 KiB */
+    int64_t nseg;          /* ceil(n * width / seg_bytes), <= 8192 */
+    int64_t elems_per_seg; /* seg_bytes / width */
+    int32_t width;         /* bytes per item: 4 or 8 */
+    int32_t reserved;
+} agg_shape;
+
+/* One column of a batch. */
+typedef struct agg_col {
+    const void* ptr;   /* device address of item 0, aligned to the item width */
+    int64_t n;         /* items, >= 0 */
+    int32_t dtype;     /* AGG_I32 / AGG_I64 / AGG_F32 */
+    int32_t op;        /* AGG_SUM .. AGG_AVG */
+    int32_t prec;      /* agg_prec (float SUM / AVG) */
+    int32_t reserved;
+} agg_col;
+
+typedef struct agg_plan_s* agg_plan_t;
+typedef struct agg_batch_s* agg_batch_t;
+
+/* ---- library ---- */
+
+/* Select and check the HIP device (must be gfx950); idempotent per device.
+ * Every other call on a device performs it implicitly. */
+int agg_init(int32_t device);
+
+/* Device facts used by the tuner: compute-unit count and gfx arch name
+ * (written NUL-terminated into arch[arch_len]). */
+int agg_device_info(int32_t device, int32_t* cu_count, char* arch, int32_t arch_len);
+
+/* The canonical reduction shape for a column of n items of dtype (pure host
+ * computation, no device needed). */
+int agg_canonical_shape(int32_t dtype, int64_t n, agg_shape* out);
+
+/* Default launch parameters for (dtype, op, prec, n, src): the tuning-cache
+ * entry of the nearest size bucket for that fold kind and source (filled by
+ * agg_autotune or agg_tune_load), else the built-in table measured on
+ * MI355X. */
+int agg_default_tune(int32_t dtype, int32_t op, int32_t prec, int64_t n, int32_t src,
+                     agg_tune* out);
+
+/* ---- single column (agg_plan / agg_run) ---- */
+
+/* Create a plan for columns of up to max_n items.  Allocates the device
+ * workspace (segment partials and a completion counter, about 64 KiB; plus
+ * staging_depth * chunk_bytes of device staging, a copy stream and events
+ * for PINNED_HOST).  tune == NULL: agg_default_tune for max_n. */
+int agg_plan(agg_plan_t* out, int32_t dtype, int32_t op, int32_t prec, int64_t max_n,
+             int32_t src, const agg_tune* tune);
+
+/* Aggregate col[0..n) into *out on `stream`.  col: an address in the memory
+ * the plan's src names, aligned to the item width, with n items readable.
+ * out: device memory or page-locked host memory, written by the GPU.
+ * Enqueues one kernel (DEVICE, ZEROCOPY) or one copy + kernel per chunk
+ * (PINNED_HOST); never allocates and never synchronises the stream, so it
+ * may be captured into a HIP graph (DEVICE, ZEROCOPY). */
+int agg_run(agg_plan_t plan, const void* col, int64_t n, agg_result* out, void* stream);
+
+/* The canonical shape and launch parameters the plan uses for n items. */
+int agg_plan_info(agg_plan_t plan, int64_t n, agg_shape* shape, agg_tune* tune);
+
+int agg_plan_destroy(agg_plan_t plan);
+
+/* ---- many columns in one launch (agg_batch) ---- */
+
+/* Build a batch over cols[0..ncols): the work table (runs of whole segments
+ * of each column), partial and result buffers, and a HIP graph holding the
+ * persistent scan kernel and the per-column combine kernel.  Column memory
+ * must stay valid and unchanged in address while the batch is used; its
+ * contents may change between runs. */
+int agg_batch_plan(agg_batch_t* out, const agg_col* cols, int32_t ncols, const agg_tune* tune);
+
+/* Launch the batch graph on `stream` and copy the ncols results into
+ * out[0..ncols) (device or page-locked host memory). */
+int agg_batch_run(agg_batch_t batch, agg_result* out, void* stream);
+
+int agg_batch_destroy(agg_batch_t batch);
+
+/* Work items, total segments and the launch parameters the batch graph uses. */
+int agg_batch_info(agg_batch_t batch, int64_t* nitems, int64_t* nseg_total, agg_tune* tune);
+
+/* Re-capture the batch graph with other launch parameters (results unchanged).
+ * Waits for the batch's previous runs to finish. */
+int agg_batch_retune(agg_batch_t batch, const agg_tune* tune);
+
+/* Time the batch graph under a fixed set of launch parameters on `stream`
+ * (waves per block x blocks per CU x loads in flight), keep the fastest and
+ * return it with its time per run in milliseconds.  Synchronises `stream`. */
+int agg_batch_autotune(agg_batch_t batch, void* stream, agg_tune* best, double* best_ms);
+
+/* ---- autotuner and tuning cache ---- */
+
+/* Time a fixed set of candidate launch parameters for (dtype, op, prec) on
+ * the caller's column col[0..n) in memory of kind `src` (device: waves per
+ * block x blocks per CU x loads in flight, then temporal vs non-temporal
+ * loads; pinned host: staging chunk x depth), on `stream`.  The fastest goes
+ * into the process-wide tuning cache under (fold kind, src, size bucket
+ * ceil(log2(n * width))) and is returned with its GB/s.  Creates and destroys
+ * temporary plans (so it allocates) and synchronises `stream`. */
+int agg_autotune(int32_t dtype, int32_t op, int32_t prec, const void* col, int64_t n, int32_t src,
+                 void* stream, agg_tune* best, double* best_gbs);
+
+/* Persist / restore the tuning cache as JSON.  A file written for another
+ * gfx arch or CU count, or one that does not parse, is rejected with
+ * AGG_E_INVALID and leaves the cache unchanged. */
+int agg_tune_save(const char* path);
+int agg_tune_load(const char* path);
+int agg_tune_clear(void);
+
+/* ---- errors ---- */
+const char* agg_strerror(int32_t code);
+int32_t agg_last_hip_error(void);  /* hipError_t of the last AGG_E_HIP on this thread */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AGG_H */

@@ -1,0 +1,379 @@
+"""MI355X (gfx950) in-memory aggregation scan: Python binding of libagg.so.
+
+This module only marshals arguments to the C ABI declared in
+``include/agg.h``; every step of the scan runs in the HIP kernels of the
+library.  PyTorch is used for device memory, pinned host memory and streams.
+There is no fallback: if ``libagg.so`` is missing or fails to load, every call
+raises ``AggError``.
+
+    import torch, paper_2606_10030_amd as agg
+    x = torch.randint(-2**20, 2**20, (1 << 20,), dtype=torch.int32, device="cuda")
+    plan = agg.Plan("i32", "sum", max_n=x.numel())
+    print(plan.run(x)["i64"])
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+from typing import Iterable, Optional, Sequence
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libagg.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "agg.h")
+
+OK, E_INVALID, E_NOMEM, E_NODEVICE, E_HIP = 0, -1, -2, -3, -4
+I32, I64, F32 = 0, 1, 2
+SUM, MIN, MAX, COUNT, AVG = 0, 1, 2, 3, 4
+PREC_NEUMAIER, PREC_F32, PREC_F64_COMBINE = 0, 1, 2
+SRC_DEVICE, SRC_PINNED_HOST, SRC_ZEROCOPY = 0, 1, 2
+
+DTYPES = {"i32": I32, "i64": I64, "f32": F32}
+OPS = {"sum": SUM, "min": MIN, "max": MAX, "count": COUNT, "avg": AVG}
+PRECS = {"neumaier": PREC_NEUMAIER, "f32": PREC_F32, "f64_combine": PREC_F64_COMBINE}
+SRCS = {"device": SRC_DEVICE, "pinned_host": SRC_PINNED_HOST, "zerocopy": SRC_ZEROCOPY}
+WIDTH = {I32: 4, I64: 8, F32: 4}
+
+
+class AggError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})" if _lib_handle else f"{what} ({code})")
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("i64", ctypes.c_int64), ("f64", ctypes.c_double), ("count", ctypes.c_int64),
+                ("is_null", ctypes.c_int32), ("prec_used", ctypes.c_int32)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("unroll", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
+                ("chunk_bytes", ctypes.c_int64), ("staging_depth", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("seg_bytes", ctypes.c_int64), ("nseg", ctypes.c_int64),
+                ("elems_per_seg", ctypes.c_int64), ("width", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Col(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("n", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("op", ctypes.c_int32), ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+RESULT_BYTES = ctypes.sizeof(Result)
+assert RESULT_BYTES == 32
+
+_lib_handle = None
+
+
+def build() -> str:
+    """Compile libagg.so in-tree with hipcc for gfx950."""
+    from ._build import build as _b
+    global _lib_handle
+    _lib_handle = None
+    return _b()
+
+
+def lib():
+    """The loaded library; raises AggError if it is not built."""
+    global _lib_handle
+    if _lib_handle is not None:
+        return _lib_handle
+    if not os.path.exists(LIB_PATH):
+        raise AggError(E_NODEVICE, f"libagg.so not built at {LIB_PATH}; call paper_2606_10030_amd.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    sig = {
+        "agg_init": ([i32], ctypes.c_int),
+        "agg_device_info": ([i32, ctypes.POINTER(i32), ctypes.c_char_p, i32], ctypes.c_int),
+        "agg_canonical_shape": ([i32, i64, ctypes.POINTER(Shape)], ctypes.c_int),
+        "agg_default_tune": ([i32, i32, i32, i64, i32, ctypes.POINTER(Tune)], ctypes.c_int),
+        "agg_plan": ([ctypes.POINTER(vp), i32, i32, i32, i64, i32, ctypes.POINTER(Tune)], ctypes.c_int),
+        "agg_run": ([vp, vp, i64, vp, vp], ctypes.c_int),
+        "agg_plan_info": ([vp, i64, ctypes.POINTER(Shape), ctypes.POINTER(Tune)], ctypes.c_int),
+        "agg_plan_destroy": ([vp], ctypes.c_int),
+        "agg_batch_plan": ([ctypes.POINTER(vp), ctypes.POINTER(Col), i32, ctypes.POINTER(Tune)], ctypes.c_int),
+        "agg_batch_run": ([vp, vp, vp], ctypes.c_int),
+        "agg_batch_destroy": ([vp], ctypes.c_int),
+        "agg_batch_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(Tune)], ctypes.c_int),
+        "agg_batch_retune": ([vp, ctypes.POINTER(Tune)], ctypes.c_int),
+        "agg_batch_autotune": ([vp, vp, ctypes.POINTER(Tune), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "agg_autotune": ([i32, i32, i32, vp, i64, i32, vp, ctypes.POINTER(Tune), ctypes.POINTER(ctypes.c_double)],
+                         ctypes.c_int),
+        "agg_tune_save": ([ctypes.c_char_p], ctypes.c_int),
+        "agg_tune_load": ([ctypes.c_char_p], ctypes.c_int),
+        "agg_tune_clear": ([], ctypes.c_int),
+        "agg_strerror": ([i32], ctypes.c_char_p),
+        "agg_last_hip_error": ([], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib_handle = L
+    return L
+
+
+def declared_symbols() -> list:
+    """Every function declared in include/agg.h."""
+    text = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(agg_\w+)\s*\(", text, re.M)))
+
+
+def strerror(code: int) -> str:
+    return lib().agg_strerror(code).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        if rc == E_HIP:
+            raise AggError(rc, f"{what} (hipError {lib().agg_last_hip_error()})")
+        raise AggError(rc, what)
+
+
+def _code(v, table, what):
+    if isinstance(v, str):
+        if v not in table:
+            raise ValueError(f"unknown {what} {v!r}")
+        return table[v]
+    return int(v)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_of_tensor(t) -> int:
+    torch = _torch()
+    m = {torch.int32: I32, torch.int64: I64, torch.float32: F32}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported column dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        return _torch().cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def canonical_shape(dtype, n: int) -> Shape:
+    s = Shape()
+    _check(lib().agg_canonical_shape(_code(dtype, DTYPES, "dtype"), n, ctypes.byref(s)), "agg_canonical_shape")
+    return s
+
+
+def default_tune(dtype, op, n: int, prec="neumaier", src="device") -> Tune:
+    t = Tune()
+    _check(lib().agg_default_tune(_code(dtype, DTYPES, "dtype"), _code(op, OPS, "op"),
+                                  _code(prec, PRECS, "prec"), n, _code(src, SRCS, "src"),
+                                  ctypes.byref(t)), "agg_default_tune")
+    return t
+
+
+def make_tune(**kw) -> Tune:
+    """A Tune from the built-in defaults with the given fields replaced."""
+    t = default_tune("i32", "sum", 1)
+    for k, v in kw.items():
+        if not hasattr(t, k):
+            raise ValueError(f"unknown tune field {k}")
+        setattr(t, k, v)
+    return t
+
+
+def autotune(dtype, op, col, n: Optional[int] = None, prec="neumaier", src="device", stream=None):
+    """Time candidate launch parameters on `col`; the fastest enters the tuning
+    cache (used by later plans without explicit parameters).  Returns (Tune, GB/s)."""
+    if isinstance(col, int):
+        ptr, nn = col, int(n)
+    else:
+        ptr, nn = col.data_ptr(), col.numel() if n is None else int(n)
+    t, g = Tune(), ctypes.c_double()
+    _check(lib().agg_autotune(_code(dtype, DTYPES, "dtype"), _code(op, OPS, "op"), _code(prec, PRECS, "prec"),
+                              ptr, nn, _code(src, SRCS, "src"), _stream_handle(stream), ctypes.byref(t),
+                              ctypes.byref(g)), "agg_autotune")
+    return t, g.value
+
+
+def tune_save(path: str) -> None:
+    _check(lib().agg_tune_save(path.encode()), "agg_tune_save")
+
+
+def tune_load(path: str) -> None:
+    _check(lib().agg_tune_load(path.encode()), "agg_tune_load")
+
+
+def tune_clear() -> None:
+    _check(lib().agg_tune_clear(), "agg_tune_clear")
+
+
+def device_info(device: int = 0) -> dict:
+    cu = ctypes.c_int32()
+    arch = ctypes.create_string_buffer(64)
+    _check(lib().agg_device_info(device, ctypes.byref(cu), arch, 64), "agg_device_info")
+    return {"cu_count": cu.value, "arch": arch.value.decode()}
+
+
+def result_dict(r: Result, dtype: int, op: int) -> dict:
+    d = {"i64": r.i64, "f64": r.f64, "count": r.count, "is_null": bool(r.is_null), "prec_used": r.prec_used}
+    if r.is_null:
+        d["value"] = None
+    elif op == COUNT or (dtype != F32 and op in (SUM, MIN, MAX)):
+        d["value"] = r.i64
+    else:
+        d["value"] = r.f64
+    return d
+
+
+def parse_results(buf, dtype_ops: Sequence) -> list:
+    """Decode a bytes-like buffer of agg_result records."""
+    raw = bytes(buf)
+    out = []
+    for i, (dt, op) in enumerate(dtype_ops):
+        r = Result.from_buffer_copy(raw, i * RESULT_BYTES)
+        out.append(result_dict(r, dt, op))
+    return out
+
+
+class Plan:
+    """agg_plan / agg_run for one (dtype, op, prec, src) and columns of up to max_n items."""
+
+    def __init__(self, dtype, op, max_n: int, prec="neumaier", src="device", tune: Optional[Tune] = None):
+        self.dtype = _code(dtype, DTYPES, "dtype")
+        self.op = _code(op, OPS, "op")
+        self.prec = _code(prec, PRECS, "prec")
+        self.src = _code(src, SRCS, "src")
+        self.max_n = int(max_n)
+        h = ctypes.c_void_p()
+        _check(lib().agg_plan(ctypes.byref(h), self.dtype, self.op, self.prec, self.max_n, self.src,
+                              ctypes.byref(tune) if tune is not None else None), "agg_plan")
+        self._h = h
+        self._host_out = None
+
+    def info(self, n: int):
+        s, t = Shape(), Tune()
+        _check(lib().agg_plan_info(self._h, n, ctypes.byref(s), ctypes.byref(t)), "agg_plan_info")
+        return s, t
+
+    def _col_args(self, col, n):
+        if isinstance(col, int):
+            if n is None:
+                raise ValueError("n is required with a raw pointer")
+            return col, int(n)
+        dt = _dtype_of_tensor(col)
+        if dt != self.dtype:
+            raise TypeError(f"column dtype {col.dtype} does not match the plan")
+        if not col.is_contiguous():
+            raise ValueError("column must be contiguous")
+        return col.data_ptr(), col.numel() if n is None else int(n)
+
+    def enqueue(self, col, out, n: Optional[int] = None, stream=None) -> None:
+        """Enqueue agg_run writing the 32-byte result to `out` (tensor or address); no sync."""
+        ptr, nn = self._col_args(col, n)
+        optr = out if isinstance(out, int) else out.data_ptr()
+        _check(lib().agg_run(self._h, ptr, nn, optr, _stream_handle(stream)), "agg_run")
+
+    def run(self, col, n: Optional[int] = None, stream=None) -> dict:
+        """Run and wait; returns the decoded result."""
+        torch = _torch()
+        if self._host_out is None:
+            self._host_out = torch.zeros(RESULT_BYTES, dtype=torch.uint8, pin_memory=True)
+        s = _torch().cuda.current_stream() if stream is None else stream
+        self.enqueue(col, self._host_out, n=n, stream=s)
+        if isinstance(s, int):
+            torch.cuda.synchronize()
+        else:
+            s.synchronize()
+        return parse_results(self._host_out.numpy().tobytes(), [(self.dtype, self.op)])[0]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().agg_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class BatchColumn:
+    col: object          # torch tensor on the device (or an int address with n and dtype)
+    op: object
+    prec: object = "neumaier"
+    n: Optional[int] = None
+    dtype: Optional[object] = None
+
+
+class Batch:
+    """agg_batch_plan / agg_batch_run over many device columns."""
+
+    def __init__(self, columns: Iterable[BatchColumn], tune: Optional[Tune] = None):
+        cols = list(columns)
+        arr = (Col * max(1, len(cols)))()
+        self.kinds = []
+        for i, c in enumerate(cols):
+            if isinstance(c.col, int):
+                ptr, n, dt = c.col, int(c.n), _code(c.dtype, DTYPES, "dtype")
+            else:
+                ptr, n, dt = c.col.data_ptr(), c.col.numel() if c.n is None else int(c.n), _dtype_of_tensor(c.col)
+            op = _code(c.op, OPS, "op")
+            arr[i] = Col(ptr, n, dt, op, _code(c.prec, PRECS, "prec"), 0)
+            self.kinds.append((dt, op))
+        h = ctypes.c_void_p()
+        _check(lib().agg_batch_plan(ctypes.byref(h), arr, len(cols),
+                                    ctypes.byref(tune) if tune is not None else None), "agg_batch_plan")
+        self._h = h
+        self.ncols = len(cols)
+        self._host_out = None
+
+    def enqueue(self, out, stream=None) -> None:
+        optr = out if isinstance(out, int) else out.data_ptr()
+        _check(lib().agg_batch_run(self._h, optr, _stream_handle(stream)), "agg_batch_run")
+
+    def info(self) -> dict:
+        ni, ns, t = ctypes.c_int64(), ctypes.c_int64(), Tune()
+        _check(lib().agg_batch_info(self._h, ctypes.byref(ni), ctypes.byref(ns), ctypes.byref(t)), "agg_batch_info")
+        return {"nitems": ni.value, "nseg_total": ns.value, "tune": t.as_dict()}
+
+    def retune(self, tune: Tune) -> None:
+        _check(lib().agg_batch_retune(self._h, ctypes.byref(tune)), "agg_batch_retune")
+
+    def autotune(self, stream=None):
+        t, ms = Tune(), ctypes.c_double()
+        _check(lib().agg_batch_autotune(self._h, _stream_handle(stream), ctypes.byref(t), ctypes.byref(ms)),
+               "agg_batch_autotune")
+        return t, ms.value
+
+    def run(self, stream=None) -> list:
+        torch = _torch()
+        if self._host_out is None:
+            self._host_out = torch.zeros(max(1, self.ncols) * RESULT_BYTES, dtype=torch.uint8, pin_memory=True)
+        s = torch.cuda.current_stream() if stream is None else stream
+        self.enqueue(self._host_out, stream=s)
+        s.synchronize()
+        return parse_results(self._host_out.numpy().tobytes(), self.kinds)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().agg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

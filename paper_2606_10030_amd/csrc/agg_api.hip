@@ -1,0 +1,697 @@
+// Host runtime of libagg.so: the C ABI declared in include/agg.h.
+//
+// Plans own their workspaces (segment partials, completion counter, and for
+// pinned-host sources a device staging ring, a copy stream and events), so
+// agg_run only validates, picks a kernel and enqueues.  Batches own a work
+// table, partials, results and a captured HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "agg.h"
+#include "agg_internal.hpp"
+
+namespace agg {
+
+int kind_of(int32_t dtype, int32_t op, int32_t prec) {
+  if (op == AGG_COUNT) {
+    if (dtype == AGG_I32 || dtype == AGG_F32) return K_COUNT_4;
+    if (dtype == AGG_I64) return K_COUNT_8;
+    return -1;
+  }
+  const bool sum = op == AGG_SUM || op == AGG_AVG;
+  if (!sum && op != AGG_MIN && op != AGG_MAX) return -1;
+  switch (dtype) {
+    case AGG_I32: return sum ? K_SUM_I32 : (op == AGG_MIN ? K_MIN_I32 : K_MAX_I32);
+    case AGG_I64: return sum ? K_SUM_I64 : (op == AGG_MIN ? K_MIN_I64 : K_MAX_I64);
+    case AGG_F32:
+      if (!sum) return op == AGG_MIN ? K_MIN_F32 : K_MAX_F32;
+      if (prec == AGG_PREC_NEUMAIER) return K_SUM_F32_NEU;
+      if (prec == AGG_PREC_F32) return K_SUM_F32_PLAIN;
+      if (prec == AGG_PREC_F64_COMBINE) return K_SUM_F32_F64C;
+      return -1;
+    default: return -1;
+  }
+}
+
+int width_of(int32_t dtype) {
+  return dtype == AGG_I64 ? 8 : (dtype == AGG_I32 || dtype == AGG_F32) ? 4 : 0;
+}
+
+int unroll_index(int32_t unroll) {
+  return unroll == 4 ? 0 : unroll == 8 ? 1 : unroll == 16 ? 2 : unroll == 32 ? 3 : -1;
+}
+
+}  // namespace agg
+
+using namespace agg;
+
+namespace {
+
+thread_local int32_t g_last_hip = 0;
+
+#define HIPCHK(expr)                                  \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) {                           \
+      g_last_hip = (int32_t)e_;                       \
+      return AGG_E_HIP;                               \
+    }                                                 \
+  } while (0)
+
+constexpr int kMaxDevices = 64;
+constexpr int64_t kMaxItems = (int64_t)1 << 40;  // keeps n * width far from overflow
+constexpr int64_t kItemBytes = 256 * 1024;        // batch work item: about this many bytes
+
+struct DeviceInfo {
+  bool checked = false;
+  int status = AGG_E_NODEVICE;
+  int cu = 0;
+  char arch[64] = {0};
+};
+std::mutex g_mu;
+DeviceInfo g_dev[kMaxDevices];
+
+int device_check(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return AGG_E_INVALID;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceInfo& d = g_dev[dev];
+  if (d.checked) return d.status;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || dev >= count) {
+    (void)hipGetLastError();
+    d.checked = true;
+    d.status = AGG_E_NODEVICE;
+    return d.status;
+  }
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) {
+    g_last_hip = (int32_t)e;
+    return AGG_E_HIP;
+  }
+  std::snprintf(d.arch, sizeof d.arch, "%s", prop.gcnArchName);
+  d.cu = prop.multiProcessorCount;
+  d.checked = true;
+  d.status = std::strncmp(d.arch, "gfx950", 6) == 0 ? AGG_OK : AGG_E_NODEVICE;
+  return d.status;
+}
+
+int current_device(int* dev) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+    (void)hipGetLastError();
+    return AGG_E_NODEVICE;
+  }
+  HIPCHK(hipGetDevice(dev));
+  return device_check(*dev);
+}
+
+}  // namespace
+
+bool agg::tune_is_valid(const agg_tune& t) {
+  const int w = t.waves_per_block;
+  return (w == 1 || w == 2 || w == 4 || w == 8 || w == 16) &&
+         t.blocks_per_cu >= 1 && t.blocks_per_cu <= 32 && unroll_index(t.unroll) >= 0 &&
+         (t.nontemporal == 0 || t.nontemporal == 1) && t.chunk_bytes >= (1 << 20) &&
+         t.chunk_bytes <= ((int64_t)1 << 32) && t.staging_depth >= 2 && t.staging_depth <= 4;
+}
+
+namespace {
+
+bool valid_tune(const agg_tune& t) { return tune_is_valid(t); }
+
+// Launch parameters for a kind: the tuning cache, else the built-in table.
+void tune_for(int kind, int32_t src, int64_t bytes, agg_tune* t) {
+  if (!tune_cache_lookup(kind, src, bytes, t)) builtin_tune_for(kind, t);
+}
+
+// Batches mix kinds; two waves per CU with 16 loads in flight suits all of
+// the plain kinds (agg_batch_autotune refines it).
+void batch_builtin_tune(agg_tune* t) { builtin_tune_for(K_SUM_I32, t); }
+
+// The memory behind [p, p + bytes) must be of the kind `src` names.
+int check_pointer(const void* p, int64_t bytes, int32_t src, int dev) {
+  hipPointerAttribute_t at;
+  std::memset(&at, 0, sizeof at);
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return AGG_E_INVALID;
+  }
+  if (src == AGG_SRC_DEVICE) {
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged) return AGG_E_INVALID;
+    if (at.type == hipMemoryTypeDevice && at.device != dev) return AGG_E_INVALID;
+  } else {
+    if (at.type != hipMemoryTypeHost) return AGG_E_INVALID;
+  }
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess && base) {
+    const char* b = static_cast<const char*>(base);
+    const char* q = static_cast<const char*>(p);
+    if (q < b || q + bytes > b + size) return AGG_E_INVALID;
+  } else {
+    // Without a known extent the scan could read past the allocation.
+    (void)hipGetLastError();
+    return AGG_E_INVALID;
+  }
+  return AGG_OK;
+}
+
+// A result buffer: device memory of `dev` or page-locked host memory, with
+// room for `bytes` bytes.
+int check_out_pointer(const void* p, int64_t bytes, int dev) {
+  hipPointerAttribute_t at;
+  std::memset(&at, 0, sizeof at);
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return AGG_E_INVALID;
+  }
+  if (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged)
+    return check_pointer(p, bytes, AGG_SRC_DEVICE, dev);
+  if (at.type == hipMemoryTypeHost) return check_pointer(p, bytes, AGG_SRC_PINNED_HOST, dev);
+  return AGG_E_INVALID;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+void shape_of(int32_t dtype, int64_t n, agg_shape* s) {
+  const int w = width_of(dtype);
+  const int64_t bytes = n * w;
+  int64_t seg = kSegMin;
+  const int64_t target = ceil_div(bytes, kSegTarget);
+  while (seg < target) seg <<= 1;
+  s->seg_bytes = seg;
+  s->nseg = ceil_div(bytes, seg);
+  s->elems_per_seg = seg / w;
+  s->width = w;
+  s->reserved = 0;
+}
+
+int grid_for(const agg_tune& t, int cu, int64_t nseg) {
+  const int64_t need = ceil_div(std::max<int64_t>(nseg, 1), t.waves_per_block);
+  return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)t.blocks_per_cu * cu, need));
+}
+
+int launch(const void* fn, int grid, int block, void* args, hipStream_t stream) {
+  void* kargs[] = {args};
+  HIPCHK(hipLaunchKernel(fn, dim3(grid), dim3(block), kargs, 0, stream));
+  return AGG_OK;
+}
+
+}  // namespace
+
+struct agg_plan_s {
+  int device = 0;
+  int32_t dtype = 0, op = 0, prec = 0, src = 0;
+  int64_t max_n = 0;
+  bool tune_given = false;
+  agg_tune tune{};
+  int kind = -1;
+  int width = 0;
+  void* ws = nullptr;             // partial slots + completion counter
+  uint64_t* part = nullptr;
+  unsigned int* ticket = nullptr;
+  // pinned-host staging
+  int depth = 0;
+  int64_t stage_bytes = 0;
+  char* stage[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t copied[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t consumed[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t start = nullptr;     // orders the copies after earlier work on the caller's stream
+  bool slot_used[4] = {false, false, false, false};
+};
+
+struct agg_batch_s {
+  int device = 0;
+  int32_t ncols = 0;
+  agg_tune tune{};
+  int64_t nitems = 0;
+  int64_t nslots = 0;
+  void* ws = nullptr;
+  BatchColDev* dcols = nullptr;
+  WorkItem* ditems = nullptr;
+  uint64_t* dpart = nullptr;
+  agg_result* dres = nullptr;
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void plan_release(agg_plan_s* p) {
+  if (!p) return;
+  for (int i = 0; i < 4; ++i) {
+    if (p->copied[i]) (void)hipEventDestroy(p->copied[i]);
+    if (p->consumed[i]) (void)hipEventDestroy(p->consumed[i]);
+    if (p->stage[i]) (void)hipFree(p->stage[i]);
+  }
+  if (p->start) (void)hipEventDestroy(p->start);
+  if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
+  if (p->ws) (void)hipFree(p->ws);
+  delete p;
+}
+
+void batch_release(agg_batch_s* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  if (b->ws) (void)hipFree(b->ws);
+  delete b;
+}
+
+int alloc_device(void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return AGG_E_NOMEM;
+  }
+  HIPCHK(e);
+  return AGG_OK;
+}
+
+#define RET_IF(x)            \
+  do {                       \
+    int rc_ = (x);           \
+    if (rc_ != AGG_OK) {     \
+      return rc_;            \
+    }                        \
+  } while (0)
+
+int plan_create(agg_plan_s* p) {
+  const size_t ws_bytes = (size_t)kSegTarget * 8 + 256;
+  RET_IF(alloc_device(&p->ws, ws_bytes));
+  p->part = static_cast<uint64_t*>(p->ws);
+  p->ticket = reinterpret_cast<unsigned int*>(static_cast<char*>(p->ws) + (size_t)kSegTarget * 8);
+  HIPCHK(hipMemset(p->ws, 0, ws_bytes));
+  if (p->src == AGG_SRC_PINNED_HOST) {
+    agg_shape s;
+    shape_of(p->dtype, p->max_n, &s);
+    p->depth = p->tune.staging_depth;
+    p->stage_bytes = std::max<int64_t>(p->tune.chunk_bytes, s.seg_bytes);
+    p->stage_bytes = std::min<int64_t>(p->stage_bytes, std::max<int64_t>(s.nseg, 1) * s.seg_bytes);
+    for (int i = 0; i < p->depth; ++i) {
+      RET_IF(alloc_device(reinterpret_cast<void**>(&p->stage[i]), (size_t)p->stage_bytes));
+      HIPCHK(hipEventCreateWithFlags(&p->copied[i], hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&p->consumed[i], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&p->start, hipEventDisableTiming));
+    HIPCHK(hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking));
+  }
+  HIPCHK(hipDeviceSynchronize());
+  return AGG_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Capture the batch graph for launch parameters t: the persistent scan over
+// the work table, then one combine workgroup per column.  Replaces any
+// previous graph.
+int batch_capture(agg_batch_s* b, const agg_tune& t) {
+  BatchArgs ba;
+  ba.cols = b->dcols;
+  ba.items = b->ditems;
+  ba.nitems = b->nitems;
+  ba.part = b->dpart;
+  ba.results = b->dres;
+  const void* scan_fn = batch_scan_kernel_ptr(t.unroll, t.nontemporal != 0);
+  if (!scan_fn) return AGG_E_INVALID;
+  const int grid = grid_for(t, g_dev[b->device].cu, b->nitems);
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  HIPCHK(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  if (b->nitems > 0) {
+    void* kargs[] = {&ba};
+    e = hipLaunchKernel(scan_fn, dim3(grid), dim3(64 * t.waves_per_block), kargs, 0, b->capture_stream);
+  }
+  if (e == hipSuccess && b->ncols > 0) {
+    int64_t nc = b->ncols;
+    void* kargs2[] = {&ba, &nc};
+    e = hipLaunchKernel(batch_combine_kernel_ptr(), dim3(b->ncols), dim3(256), kargs2, 0, b->capture_stream);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(b->capture_stream, &g);
+  b->graph = g;
+  HIPCHK(e);
+  HIPCHK(e2);
+  HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  b->tune = t;
+  return AGG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int agg_init(int32_t device) { return device_check(device); }
+
+int agg_device_info(int32_t device, int32_t* cu_count, char* arch, int32_t arch_len) {
+  const int rc = device_check(device);
+  if (rc != AGG_OK && rc != AGG_E_NODEVICE) return rc;
+  if (!g_dev[device].checked || g_dev[device].cu == 0) return AGG_E_NODEVICE;
+  if (cu_count) *cu_count = g_dev[device].cu;
+  if (arch && arch_len > 0) std::snprintf(arch, (size_t)arch_len, "%s", g_dev[device].arch);
+  return rc;
+}
+
+int agg_canonical_shape(int32_t dtype, int64_t n, agg_shape* out) {
+  if (!out || width_of(dtype) == 0 || n < 0 || n > kMaxItems) return AGG_E_INVALID;
+  shape_of(dtype, n, out);
+  return AGG_OK;
+}
+
+int agg_default_tune(int32_t dtype, int32_t op, int32_t prec, int64_t n, int32_t src, agg_tune* out) {
+  const int kind = kind_of(dtype, op, prec);
+  if (!out || kind < 0 || n < 0 || n > kMaxItems || src < AGG_SRC_DEVICE || src > AGG_SRC_ZEROCOPY)
+    return AGG_E_INVALID;
+  tune_for(kind, src, n * width_of(dtype), out);
+  return AGG_OK;
+}
+
+int agg_plan(agg_plan_t* out, int32_t dtype, int32_t op, int32_t prec, int64_t max_n, int32_t src,
+             const agg_tune* tune) {
+  if (!out) return AGG_E_INVALID;
+  *out = nullptr;
+  const int kind = kind_of(dtype, op, prec);
+  if (kind < 0 || max_n < 0 || max_n > kMaxItems || src < AGG_SRC_DEVICE || src > AGG_SRC_ZEROCOPY)
+    return AGG_E_INVALID;
+  agg_tune t;
+  if (tune) {
+    t = *tune;
+    if (!valid_tune(t)) return AGG_E_INVALID;
+  } else {
+    agg_default_tune(dtype, op, prec, max_n, src, &t);
+  }
+  int dev = 0;
+  RET_IF(current_device(&dev));
+  agg_plan_s* p = new (std::nothrow) agg_plan_s();
+  if (!p) return AGG_E_NOMEM;
+  p->device = dev;
+  p->dtype = dtype; p->op = op; p->prec = prec; p->src = src;
+  p->max_n = max_n;
+  p->tune = t;
+  p->tune_given = tune != nullptr;
+  p->kind = kind;
+  p->width = width_of(dtype);
+  const int rc = plan_create(p);
+  if (rc != AGG_OK) {
+    plan_release(p);
+    return rc;
+  }
+  *out = p;
+  return AGG_OK;
+}
+
+int agg_plan_info(agg_plan_t plan, int64_t n, agg_shape* shape, agg_tune* tune) {
+  if (!plan || n < 0 || n > plan->max_n) return AGG_E_INVALID;
+  if (shape) shape_of(plan->dtype, n, shape);
+  if (tune) *tune = plan->tune;
+  return AGG_OK;
+}
+
+int agg_run(agg_plan_t p, const void* col, int64_t n, agg_result* out, void* stream_v) {
+  if (!p || !out || n < 0 || n > p->max_n || (n > 0 && !col)) return AGG_E_INVALID;
+  if (n > 0 && reinterpret_cast<uintptr_t>(col) % (uintptr_t)p->width != 0) return AGG_E_INVALID;
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  agg_shape s;
+  shape_of(p->dtype, n, &s);
+  const int64_t bytes = n * p->width;
+  if (n > 0) RET_IF(check_pointer(col, bytes, p->src == AGG_SRC_ZEROCOPY ? AGG_SRC_PINNED_HOST : p->src,
+                                  p->device));
+  RET_IF(check_out_pointer(out, sizeof(agg_result), p->device));
+  const agg_tune& t = p->tune;
+  const int cu = g_dev[p->device].cu;
+  const bool aligned = (reinterpret_cast<uintptr_t>(col) & 15) == 0;
+  const bool is_float_sum = p->dtype == AGG_F32 && (p->op == AGG_SUM || p->op == AGG_AVG);
+
+  ScanArgs a;
+  a.col_bytes = bytes;
+  a.seg_bytes = s.seg_bytes;
+  a.nseg = s.nseg;
+  a.part = p->part;
+  a.ticket = p->ticket;
+  a.out = out;
+  a.n = n;
+  a.is_avg = p->op == AGG_AVG;
+  a.prec_used = is_float_sum ? p->prec : -1;
+
+  if (p->src != AGG_SRC_PINNED_HOST || n == 0) {
+    const void* fn = scan_kernel_ptr(p->kind, t.unroll, t.nontemporal != 0, aligned || n == 0);
+    if (!fn) return AGG_E_INVALID;
+    a.base = static_cast<const char*>(col);
+    a.seg_lo = 0;
+    a.seg_hi = s.nseg;
+    a.base_seg = 0;
+    return launch(fn, grid_for(t, cu, s.nseg), 64 * t.waves_per_block, &a, stream);
+  }
+
+  // Pinned host: copy chunks of whole segments into the staging ring on the
+  // copy stream while the scan of earlier chunks runs on `stream`.
+  const void* fn = scan_kernel_ptr(p->kind, t.unroll, t.nontemporal != 0, true);
+  if (!fn) return AGG_E_INVALID;
+  const int64_t cs = std::max<int64_t>(1, p->stage_bytes / s.seg_bytes);
+  const int64_t nchunks = ceil_div(s.nseg, cs);
+  const char* host = static_cast<const char*>(col);
+  HIPCHK(hipEventRecord(p->start, stream));
+  HIPCHK(hipStreamWaitEvent(p->copy_stream, p->start, 0));
+  for (int64_t c = 0; c < nchunks; ++c) {
+    const int slot = (int)(c % p->depth);
+    const int64_t lo = c * cs, hi = std::min(s.nseg, lo + cs);
+    const int64_t b0 = lo * s.seg_bytes;
+    const int64_t nb = std::min(bytes, hi * s.seg_bytes) - b0;
+    if (p->slot_used[slot]) HIPCHK(hipStreamWaitEvent(p->copy_stream, p->consumed[slot], 0));
+    HIPCHK(hipMemcpyAsync(p->stage[slot], host + b0, (size_t)nb, hipMemcpyHostToDevice, p->copy_stream));
+    HIPCHK(hipEventRecord(p->copied[slot], p->copy_stream));
+    HIPCHK(hipStreamWaitEvent(stream, p->copied[slot], 0));
+    a.base = p->stage[slot];
+    a.seg_lo = lo;
+    a.seg_hi = hi;
+    a.base_seg = lo;
+    RET_IF(launch(fn, grid_for(t, cu, hi - lo), 64 * t.waves_per_block, &a, stream));
+    HIPCHK(hipEventRecord(p->consumed[slot], stream));
+    p->slot_used[slot] = true;
+  }
+  return AGG_OK;
+}
+
+int agg_plan_destroy(agg_plan_t plan) {
+  if (!plan) return AGG_E_INVALID;
+  if (plan->copy_stream) (void)hipStreamSynchronize(plan->copy_stream);
+  (void)hipDeviceSynchronize();
+  plan_release(plan);
+  return AGG_OK;
+}
+
+// ------------------------------------------------------------ batch
+int agg_batch_plan(agg_batch_t* out, const agg_col* cols, int32_t ncols, const agg_tune* tune) {
+  if (!out || ncols < 0 || (ncols > 0 && !cols)) return AGG_E_INVALID;
+  *out = nullptr;
+  agg_tune t;
+  if (tune) {
+    t = *tune;
+    if (!valid_tune(t)) return AGG_E_INVALID;
+  } else {
+    batch_builtin_tune(&t);
+  }
+  for (int32_t i = 0; i < ncols; ++i) {  // host-side checks first
+    const agg_col& c = cols[i];
+    const int w = width_of(c.dtype);
+    if (kind_of(c.dtype, c.op, c.prec) < 0 || c.n < 0 || c.n > kMaxItems || (c.n > 0 && !c.ptr))
+      return AGG_E_INVALID;
+    if (c.n > 0 && reinterpret_cast<uintptr_t>(c.ptr) % (uintptr_t)w != 0) return AGG_E_INVALID;
+  }
+  int dev = 0;
+  RET_IF(current_device(&dev));
+
+  std::vector<BatchColDev> hc((size_t)ncols);
+  std::vector<WorkItem> items;
+  int64_t slots = 0;
+  for (int32_t i = 0; i < ncols; ++i) {
+    const agg_col& c = cols[i];
+    const int kind = kind_of(c.dtype, c.op, c.prec);
+    const int w = width_of(c.dtype);
+    if (c.n > 0) RET_IF(check_pointer(c.ptr, c.n * w, AGG_SRC_DEVICE, dev));
+    agg_shape s;
+    shape_of(c.dtype, c.n, &s);
+    BatchColDev& d = hc[(size_t)i];
+    d.ptr = static_cast<const char*>(c.ptr);
+    d.col_bytes = c.n * w;
+    d.seg_bytes = s.seg_bytes;
+    d.nseg = s.nseg;
+    d.part_off = slots;
+    d.n = c.n;
+    d.kind = kind;
+    d.is_avg = c.op == AGG_AVG;
+    d.prec_used = (c.dtype == AGG_F32 && (c.op == AGG_SUM || c.op == AGG_AVG)) ? c.prec : -1;
+    d.aligned = (reinterpret_cast<uintptr_t>(c.ptr) & 15) == 0;
+    slots += s.nseg;
+    const int64_t per = std::max<int64_t>(1, kItemBytes / s.seg_bytes);
+    for (int64_t lo = 0; lo < s.nseg; lo += per) {
+      WorkItem it;
+      it.col = i;
+      it.seg_lo = (int32_t)lo;
+      it.seg_hi = (int32_t)std::min<int64_t>(s.nseg, lo + per);
+      it.reserved = 0;
+      items.push_back(it);
+    }
+  }
+
+  agg_batch_s* b = new (std::nothrow) agg_batch_s();
+  if (!b) return AGG_E_NOMEM;
+  b->device = dev;
+  b->ncols = ncols;
+  b->tune = t;
+  b->nitems = (int64_t)items.size();
+  b->nslots = slots;
+  auto fail = [&](int rc) {
+    batch_release(b);
+    return rc;
+  };
+  const size_t cols_b = sizeof(BatchColDev) * (size_t)std::max(ncols, 1);
+  const size_t items_b = sizeof(WorkItem) * (size_t)std::max<int64_t>(b->nitems, 1);
+  const size_t part_b = 8 * (size_t)std::max<int64_t>(slots, 1);
+  const size_t res_b = sizeof(agg_result) * (size_t)std::max(ncols, 1);
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t total = up(cols_b) + up(items_b) + up(part_b) + up(res_b);
+  int rc = alloc_device(&b->ws, total);
+  if (rc != AGG_OK) return fail(rc);
+  char* base = static_cast<char*>(b->ws);
+  b->dcols = reinterpret_cast<BatchColDev*>(base);
+  b->ditems = reinterpret_cast<WorkItem*>(base + up(cols_b));
+  b->dpart = reinterpret_cast<uint64_t*>(base + up(cols_b) + up(items_b));
+  b->dres = reinterpret_cast<agg_result*>(base + up(cols_b) + up(items_b) + up(part_b));
+  auto hip_fail = [&](hipError_t e) {
+    g_last_hip = (int32_t)e;
+    return fail(AGG_E_HIP);
+  };
+  hipError_t e;
+  if (ncols > 0 && (e = hipMemcpy(b->dcols, hc.data(), sizeof(BatchColDev) * (size_t)ncols,
+                                  hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e);
+  if (b->nitems > 0 && (e = hipMemcpy(b->ditems, items.data(), sizeof(WorkItem) * (size_t)b->nitems,
+                                      hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e);
+
+  const int rc2 = batch_capture(b, t);
+  if (rc2 != AGG_OK) return fail(rc2);
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e);
+  *out = b;
+  return AGG_OK;
+}
+
+int agg_batch_run(agg_batch_t b, agg_result* out, void* stream_v) {
+  if (!b || (b->ncols > 0 && !out)) return AGG_E_INVALID;
+  if (b->ncols == 0) return AGG_OK;
+  RET_IF(check_out_pointer(out, (int64_t)sizeof(agg_result) * b->ncols, b->device));
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  HIPCHK(hipGraphLaunch(b->exec, stream));
+  HIPCHK(hipMemcpyAsync(out, b->dres, sizeof(agg_result) * (size_t)b->ncols, hipMemcpyDefault, stream));
+  return AGG_OK;
+}
+
+int agg_batch_destroy(agg_batch_t b) {
+  if (!b) return AGG_E_INVALID;
+  (void)hipDeviceSynchronize();
+  batch_release(b);
+  return AGG_OK;
+}
+
+int agg_batch_retune(agg_batch_t b, const agg_tune* tune) {
+  if (!b || !tune || !valid_tune(*tune)) return AGG_E_INVALID;
+  HIPCHK(hipStreamSynchronize(b->capture_stream));
+  return batch_capture(b, *tune);
+}
+
+int agg_batch_info(agg_batch_t b, int64_t* nitems, int64_t* nseg_total, agg_tune* tune) {
+  if (!b) return AGG_E_INVALID;
+  if (nitems) *nitems = b->nitems;
+  if (nseg_total) *nseg_total = b->nslots;
+  if (tune) *tune = b->tune;
+  return AGG_OK;
+}
+
+int agg_batch_autotune(agg_batch_t b, void* stream_v, agg_tune* best, double* best_ms_out) {
+  if (!b) return AGG_E_INVALID;
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  if (b->ncols == 0) {
+    if (best) *best = b->tune;
+    if (best_ms_out) *best_ms_out = 0.0;
+    return AGG_OK;
+  }
+  const int wb[][2] = {{1, 2}, {2, 1}, {4, 1}, {1, 3}, {2, 2}, {4, 2}, {8, 1}, {1, 4}};
+  agg_tune best_t = b->tune;
+  double best_ms = -1.0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    HIPCHK(e);
+  }
+  int rc = AGG_OK;
+  for (int u : {8, 16, 32}) {
+    for (auto& p : wb) {
+      agg_tune t = b->tune;
+      t.unroll = u;
+      t.waves_per_block = p[0];
+      t.blocks_per_cu = p[1];
+      rc = batch_capture(b, t);
+      if (rc != AGG_OK) break;
+      if ((e = hipGraphLaunch(b->exec, stream)) != hipSuccess) { g_last_hip = (int32_t)e; rc = AGG_E_HIP; break; }
+      if ((e = hipEventRecord(e0, stream)) != hipSuccess) { g_last_hip = (int32_t)e; rc = AGG_E_HIP; break; }
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) { g_last_hip = (int32_t)e; rc = AGG_E_HIP; break; }
+      if (best_ms < 0 || ms / 3 < best_ms) {
+        best_ms = ms / 3;
+        best_t = t;
+      }
+    }
+    if (rc != AGG_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != AGG_OK) return rc;
+  RET_IF(batch_capture(b, best_t));
+  if (best) *best = best_t;
+  if (best_ms_out) *best_ms_out = best_ms;
+  return AGG_OK;
+}
+
+const char* agg_strerror(int32_t code) {
+  switch (code) {
+    case AGG_OK: return "ok";
+    case AGG_E_INVALID: return "invalid argument";
+    case AGG_E_NOMEM: return "out of device memory";
+    case AGG_E_NODEVICE: return "no gfx950 HIP device";
+    case AGG_E_HIP: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+int32_t agg_last_hip_error(void) { return g_last_hip; }
+
+}  // extern "C"

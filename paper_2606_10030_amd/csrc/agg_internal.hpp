@@ -1,0 +1,83 @@
+// Internal interface between the kernels (agg_kernels.hip) and the host
+// runtime (agg_api.hip).  Not part of the public ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include "agg.h"
+
+namespace agg {
+
+// Fold kinds: one per (item type, function, precision).  AVG folds as SUM.
+enum Kind : int {
+  K_SUM_I32 = 0, K_MIN_I32, K_MAX_I32,
+  K_SUM_I64, K_MIN_I64, K_MAX_I64,
+  K_SUM_F32_PLAIN, K_SUM_F32_F64C, K_SUM_F32_NEU,
+  K_MIN_F32, K_MAX_F32,
+  K_COUNT_4, K_COUNT_8,
+  K_NUM
+};
+
+// One launch of the single-column scan over segments [seg_lo, seg_hi).
+struct ScanArgs {
+  const char* base;      // address of segment base_seg of the column
+  int64_t col_bytes;     // n * width
+  int64_t seg_bytes;     // canonical segment size
+  int64_t seg_lo, seg_hi;
+  int64_t base_seg;      // segment index that `base` points at
+  int64_t nseg;          // segments of the whole column
+  void* part;            // nseg segment partials (8-byte slots)
+  unsigned int* ticket;  // segments completed so far; reset to 0 by the combiner
+  agg_result* out;
+  int64_t n;
+  int32_t is_avg;
+  int32_t prec_used;
+};
+
+// One column of a batch, as the device sees it.
+struct BatchColDev {
+  const char* ptr;
+  int64_t col_bytes;
+  int64_t seg_bytes;
+  int64_t nseg;
+  int64_t part_off;      // first 8-byte partial slot of this column
+  int64_t n;
+  int32_t kind;
+  int32_t is_avg;
+  int32_t prec_used;
+  int32_t aligned;       // ptr is 16-byte aligned
+};
+
+// A run of whole segments [seg_lo, seg_hi) of one column: the unit of work
+// of the persistent batch kernel.
+struct WorkItem {
+  int32_t col;
+  int32_t seg_lo;
+  int32_t seg_hi;
+  int32_t reserved;
+};
+
+struct BatchArgs {
+  const BatchColDev* cols;
+  const WorkItem* items;
+  int64_t nitems;
+  uint64_t* part;
+  agg_result* results;
+};
+
+int kind_of(int32_t dtype, int32_t op, int32_t prec);  // -1 if invalid
+int width_of(int32_t dtype);                          // 4 or 8, 0 if invalid
+int unroll_index(int32_t unroll);                      // 0..3 for 4,8,16,32; -1 otherwise
+
+bool tune_is_valid(const agg_tune& t);
+bool tune_cache_lookup(int kind, int32_t src, int64_t bytes, agg_tune* out);
+void builtin_tune_for(int kind, agg_tune* out);
+
+const void* scan_kernel_ptr(int kind, int unroll, bool nontemporal, bool aligned);
+const void* batch_scan_kernel_ptr(int unroll, bool nontemporal);
+const void* batch_combine_kernel_ptr();
+
+constexpr int64_t kSegMin = 16 * 1024;
+constexpr int64_t kSegTarget = 8192;   // at most this many segments per column
+
+}  // namespace agg

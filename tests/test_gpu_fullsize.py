@@ -1,0 +1,136 @@
+"""GPU parity at full workload sizes, in the launch configuration the
+benchmark times (default plans): 2^30-item columns of every dtype and
+distribution with every function (preloaded and from pinned host memory),
+the float32 precision study with heavy cancellation, 64-bit indexing past
+2^31 and 2^32 items, and the paper-shaped key-column sweep.  Every result is
+checked against the CPU oracle on the full column."""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from aggcheck import check, same_bits
+
+pytestmark = pytest.mark.gpu
+
+N = 1 << 30
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def agg():
+    import torch
+    import paper_2606_10030_amd as agg
+    assert torch.cuda.is_available()
+    return agg
+
+
+def pinned_column(n, dtype, dist, seed, lo=0, hi=0):
+    import torch
+    tdt = {"i32": torch.int32, "i64": torch.int64, "f32": torch.float32}[dtype]
+    h = torch.empty(n, dtype=tdt, pin_memory=True)
+    datagen.fill_ptr(h.data_ptr(), n, dtype, dist, seed, lo, hi)
+    return h
+
+
+def free():
+    import torch
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "sorted"])
+@pytest.mark.parametrize("dtype", ["i32", "i64", "f32"])
+def test_full_size_grid(agg, dtype, dist):
+    t0 = time.time()
+    seed = {"i32": 2, "i64": 5, "f32": 8}[dtype] + {"uniform": 0, "zipf": 1, "sorted": 2}[dist]
+    h = pinned_column(N, dtype, dist, seed)
+    x = h.numpy()
+    d = h.to("cuda")
+    say(f"{dtype} {dist}: generated + copied in {time.time() - t0:.1f}s")
+    cases = [(op, "neumaier") for op in ("sum", "min", "max", "count", "avg")]
+    if dtype == "f32":
+        cases += [("sum", "f32"), ("sum", "f64_combine"), ("avg", "f32"), ("avg", "f64_combine")]
+    for op, prec in cases:
+        plan = agg.Plan(dtype, op, max_n=N, prec=prec)
+        got = plan.run(d)
+        rep = check(x, dtype, op, prec, got, ctx=f"{dtype} {dist} {op} {prec}")
+        if dist == "uniform" and op in ("sum", "min"):
+            hp = agg.Plan(dtype, op, max_n=N, prec=prec, src="pinned_host")
+            assert same_bits(got, hp.run(h)), f"{dtype} {op}: pinned-host run differs from device run"
+            hp.close()
+        if rep:
+            say(f"  {op} {prec}: rel {rep['rel']:.3e} kappa {rep['kappa']:.3e}")
+        plan.close()
+    if dist == "sorted":  # a permutation of the uniform column: integer results identical
+        u = pinned_column(N, dtype, "uniform", seed)
+        du = u.to("cuda")
+        for op in ("sum", "min", "max"):
+            if dtype == "f32" and op == "sum":
+                continue
+            assert same_bits(agg.Plan(dtype, op, max_n=N).run(d), agg.Plan(dtype, op, max_n=N).run(du))
+        assert float(x[0]) == agg.Plan(dtype, "min", max_n=N).run(d)["value"]
+        assert float(x[-1]) == agg.Plan(dtype, "max", max_n=N).run(d)["value"]
+        del du, u
+    del d, h
+    free()
+    say(f"{dtype} {dist}: done in {time.time() - t0:.1f}s")
+
+
+def test_precision_study_heavy_cancellation(agg):
+    """N(0,1) with 1% outliers of +-1e6: every mode within its a-priori bound,
+    the compensated mode within 1e-6 relative of the exact sum."""
+    h = pinned_column(N, "f32", "normal_outliers", 11)
+    x = h.numpy()
+    d = h.to("cuda")
+    report = {}
+    for prec in ("f32", "f64_combine", "neumaier"):
+        got = agg.Plan("f32", "sum", max_n=N, prec=prec).run(d)
+        rep = check(x, "f32", "sum", prec, got, ctx=f"precision {prec}")
+        report[prec] = {"value": got["f64"], **rep}
+        say(f"precision {prec}: rel {rep['rel']:.3e} abs_norm {rep['abs_norm']:.3e} kappa {rep['kappa']:.3e}")
+    assert report["neumaier"]["rel"] <= 1e-6
+    assert report["neumaier"]["rel"] <= report["f64_combine"]["rel"] + 1e-15
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, "precision_study.json"), "w") as f:
+            json.dump({"n": N, "distribution": "N(0,1) + 1% of +-1e6", "seed": 11,
+                       "exact_sum": oracle.value(x, "sum"), "modes": report}, f, indent=1)
+    del d, h
+    free()
+
+
+@pytest.mark.parametrize("n", [(1 << 31) + 5, (1 << 32) + 5])
+def test_64bit_indexing(agg, n):
+    import torch
+    x = datagen.column(n, "i32", "uniform", seed=21)   # pageable: no power-of-two pinned block
+    x[n - 1] = 2**31 - 1       # extremes at the very end: past 2^31 / 2^32 items
+    x[n - 3] = -2**31
+    d = torch.from_numpy(x).to("cuda")
+    h = None
+    for op in ("sum", "min", "max", "count", "avg"):
+        got = agg.Plan("i32", op, max_n=n).run(d)
+        check(x, "i32", op, "neumaier", got, ctx=f"n={n} {op}")
+    del d, h
+    free()
+
+
+def test_paper_shaped_key_column(agg):
+    """SUM over an int32 key column uniform in [1, 1e4 * SF] with 6e6 * SF rows (SF 200)."""
+    sf = 200
+    n = 6_000_000 * sf
+    h = pinned_column(n, "i32", "uniform", 31, 1, 10_000 * sf + 1)
+    x = h.numpy()
+    d = h.to("cuda")
+    got = agg.Plan("i32", "sum", max_n=n).run(d)
+    check(x, "i32", "sum", "neumaier", got, ctx="paper-shaped SF200")
+    del d, h
+    free()

@@ -1,0 +1,193 @@
+"""GPU parity: the HIP scan through the C ABI against the CPU oracle.
+
+Sizes span one partial wave load up to hundreds of segments, with ragged
+tails; every dtype, function and float precision mode; aligned and unaligned
+column addresses; pinned-host (chunked) and zero-copy sources; many launch
+configurations (which must not change a bit); repeated runs; and the error
+paths of agg_run on a real device.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from aggcheck import check, same_bits
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [0, 1, 2, 3, 4, 5, 15, 16, 17, 63, 64, 65, 255, 256, 257, 1023, 1024, 1025, 4095, 4096,
+         4097, 16383, 65539, 2**20, 2**20 + 13, 3 * 2**20 + 5, 10_000_019]
+CASES = [("i32", op, "neumaier") for op in ("sum", "min", "max", "count", "avg")] + \
+        [("i64", op, "neumaier") for op in ("sum", "min", "max", "count", "avg")] + \
+        [("f32", op, "neumaier") for op in ("min", "max", "count")] + \
+        [("f32", op, prec) for op in ("sum", "avg") for prec in ("neumaier", "f32", "f64_combine")]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def agg():
+    import torch
+    import paper_2606_10030_amd as agg
+    assert torch.cuda.is_available()
+    assert agg.device_info(0)["arch"].startswith("gfx950")
+    return agg
+
+
+def tdev(x: np.ndarray):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def column(dtype: str, n: int, seed: int, kind: str = "uniform") -> np.ndarray:
+    if kind == "wide" and dtype == "f32":   # heavy cancellation, magnitudes 2^-20 .. 2^20
+        r = np.random.default_rng(seed)
+        return (r.standard_normal(n) * np.exp2(r.integers(-20, 21, size=n))).astype(np.float32)
+    return datagen.column(n, dtype, kind if kind != "wide" else "uniform", seed=seed)
+
+
+@pytest.mark.parametrize("dtype,op,prec", CASES)
+def test_parity_all_sizes(agg, dtype, op, prec):
+    big = column(dtype, max(SIZES), seed=100 + len(op), kind="wide" if dtype == "f32" else "uniform")
+    # planted extremes in the middle of the longer columns
+    if dtype != "f32":
+        lo, hi = np.iinfo(big.dtype).min, np.iinfo(big.dtype).max
+        big[777_777] = lo
+        big[5_555_555] = hi
+    d = tdev(big)
+    plan = agg.Plan(dtype, op, max_n=big.size, prec=prec)
+    say(f"parity {dtype} {op} {prec}")
+    for n in SIZES:
+        got = plan.run(d[:n] if n else d[:0], n=n)
+        check(big[:n], dtype, op, prec, got, ctx=f"{dtype} {op} {prec} n={n}")
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["i32", "i64", "f32"])
+@pytest.mark.parametrize("dist", ["zipf", "sorted"])
+def test_parity_distributions(agg, dtype, dist):
+    n = 5_000_011
+    x = datagen.column(n, dtype, dist, seed=7)
+    d = tdev(x)
+    for op in ("sum", "min", "max", "avg"):
+        got = agg.Plan(dtype, op, max_n=n).run(d)
+        check(x, dtype, op, "neumaier", got, ctx=f"{dtype} {dist} {op}")
+
+
+@pytest.mark.parametrize("dtype", ["i32", "i64", "f32"])
+def test_unaligned_addresses_match_aligned_copy(agg, dtype):
+    import torch
+    x = column(dtype, 3_000_017, seed=31, kind="wide")
+    d = tdev(x)
+    for op, prec in [("sum", "neumaier"), ("sum", "f32"), ("min", "neumaier"), ("max", "neumaier"),
+                     ("avg", "f64_combine")]:
+        if dtype != "f32" and prec != "neumaier":
+            continue
+        plan = agg.Plan(dtype, op, max_n=x.size, prec=prec)
+        for off in (1, 2, 3):
+            if (off * x.itemsize) % 16 == 0:
+                continue
+            n = x.size - off - 5
+            view = d[off:off + n]
+            assert view.data_ptr() % 16 != 0
+            got = plan.run(view)
+            check(x[off:off + n], dtype, op, prec, got, ctx=f"unaligned {dtype} {op} off={off}")
+            copy = torch.empty(n + 64, dtype=d.dtype, device="cuda")[:n]
+            copy.copy_(view)
+            assert copy.data_ptr() % 16 == 0
+            assert same_bits(got, plan.run(copy)), f"{dtype} {op} {prec} off={off}: aligned copy differs"
+
+
+def test_launch_parameters_do_not_change_bits(agg):
+    x = column("f32", 7_000_003, seed=5, kind="wide")
+    d = tdev(x)
+    tunes = [dict(unroll=u, waves_per_block=w, blocks_per_cu=b, nontemporal=nt)
+             for u, w, b, nt in [(4, 4, 1, 0), (8, 4, 8, 1), (16, 4, 2, 1), (8, 8, 4, 0), (16, 16, 1, 1),
+                                 (4, 16, 32, 0), (8, 4, 32, 1)]]
+    for op, prec in [("sum", "neumaier"), ("sum", "f32"), ("sum", "f64_combine"), ("min", "neumaier")]:
+        ref = None
+        for t in tunes:
+            got = agg.Plan("f32", op, max_n=x.size, prec=prec, tune=agg.make_tune(**t)).run(d)
+            if ref is None:
+                ref = got
+                check(x, "f32", op, prec, got, ctx=f"tune {t}")
+            assert same_bits(ref, got), f"{op} {prec}: tune {t} changed the result"
+    for dtype in ("i32", "i64"):
+        xi = column(dtype, 4_000_037, seed=6)
+        di = tdev(xi)
+        for t in tunes:
+            got = agg.Plan(dtype, "sum", max_n=xi.size, tune=agg.make_tune(**t)).run(di)
+            check(xi, dtype, "sum", "neumaier", got, ctx=f"tune {t}")
+
+
+def test_repeated_runs_are_bitwise_identical(agg):
+    x = column("f32", 10_000_019, seed=9, kind="wide")
+    d = tdev(x)
+    for prec in ("neumaier", "f32", "f64_combine"):
+        plan = agg.Plan("f32", "sum", max_n=x.size, prec=prec)
+        first = plan.run(d)
+        for _ in range(10):
+            assert same_bits(first, plan.run(d))
+
+
+@pytest.mark.parametrize("src", ["pinned_host", "zerocopy"])
+@pytest.mark.parametrize("dtype", ["i32", "i64", "f32"])
+def test_host_sources_match_device(agg, src, dtype):
+    import torch
+    n = 9_000_007
+    x = column(dtype, n, seed=41, kind="wide")
+    host = torch.from_numpy(x).pin_memory()
+    d = host.to("cuda")
+    for op, prec in [("sum", "neumaier"), ("sum", "f32"), ("min", "neumaier"), ("avg", "f64_combine"),
+                     ("count", "neumaier")]:
+        if dtype != "f32" and prec != "neumaier":
+            continue
+        ref = agg.Plan(dtype, op, max_n=n, prec=prec).run(d)
+        for tune in (None, agg.make_tune(chunk_bytes=1 << 20, staging_depth=2),
+                     agg.make_tune(chunk_bytes=3 << 20, staging_depth=4, unroll=4)):
+            plan = agg.Plan(dtype, op, max_n=n, prec=prec, src=src, tune=tune)
+            for m in (n, n - 12345, 100, 0):
+                got = plan.run(host[:m] if m else host[:0], n=m)
+                if m == n:
+                    assert same_bits(ref, got), f"{src} {dtype} {op} {prec}: differs from device"
+                check(x[:m], dtype, op, prec, got, ctx=f"{src} {dtype} {op} n={m}")
+            plan.close()
+
+
+def test_result_written_to_device_memory(agg):
+    import torch
+    x = column("i64", 1_000_003, seed=3)
+    d = tdev(x)
+    plan = agg.Plan("i64", "sum", max_n=x.size)
+    out = torch.zeros(32, dtype=torch.uint8, device="cuda")
+    plan.enqueue(d, out)
+    torch.cuda.synchronize()
+    r = agg.parse_results(out.cpu().numpy().tobytes(), [(agg.I64, agg.SUM)])[0]
+    assert r["i64"] == oracle.value(x, "sum")
+
+
+def test_errors_on_device(agg):
+    import torch
+    L = agg.lib()
+    x = tdev(np.arange(1000, dtype=np.int32))
+    plan = agg.Plan("i32", "sum", max_n=1 << 20)
+    out = torch.zeros(32, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    assert L.agg_run(plan._h, x.data_ptr() + 1, 10, out.data_ptr(), s) == agg.E_INVALID   # misaligned
+    assert L.agg_run(plan._h, x.data_ptr(), (1 << 20) + 1, out.data_ptr(), s) == agg.E_INVALID  # > max_n
+    host = np.arange(1000, dtype=np.int32)                                               # pageable host
+    assert L.agg_run(plan._h, host.ctypes.data, 1000, out.data_ptr(), s) == agg.E_INVALID
+    pinned = torch.arange(1000, dtype=torch.int32).pin_memory()                          # wrong source
+    assert L.agg_run(plan._h, pinned.data_ptr(), 1000, out.data_ptr(), s) == agg.E_INVALID
+    big = agg.Plan("i32", "sum", max_n=1 << 34)
+    assert L.agg_run(big._h, x.data_ptr(), 1 << 33, out.data_ptr(), s) == agg.E_INVALID  # beyond allocation
+    hp = agg.Plan("i32", "sum", max_n=1 << 20, src="pinned_host")
+    assert L.agg_run(hp._h, x.data_ptr(), 1000, out.data_ptr(), s) == agg.E_INVALID     # device ptr to host plan
+    # the plan still works after rejected calls
+    torch.cuda.synchronize()
+    assert plan.run(x)["i64"] == 999 * 1000 // 2
