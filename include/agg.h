@@ -149,7 +149,7 @@ int agg_default_tune(int32_t dtype, int32_t op, int32_t prec, int64_t n, int32_t
 /* ---- single column (agg_plan / agg_run) ---- */
 
 /* Create a plan for columns of up to max_n items.  Allocates the device
- * workspace (segment partials and a completion counter, about 64 KiB; plus
+ * workspace (segment partials, 64 KiB; plus
  * staging_depth * chunk_bytes of device staging, a copy stream and events
  * for PINNED_HOST).  tune == NULL: agg_default_tune for max_n. */
 int agg_plan(agg_plan_t* out, int32_t dtype, int32_t op, int32_t prec, int64_t max_n,
@@ -158,7 +158,8 @@ int agg_plan(agg_plan_t* out, int32_t dtype, int32_t op, int32_t prec, int64_t m
 /* Aggregate col[0..n) into *out on `stream`.  col: an address in the memory
  * the plan's src names, aligned to the item width, with n items readable.
  * out: device memory or page-locked host memory, written by the GPU.
- * Enqueues one kernel (DEVICE, ZEROCOPY) or one copy + kernel per chunk
+ * Enqueues the scan kernel and the one-workgroup combine kernel (DEVICE,
+ * ZEROCOPY), or one copy + scan kernel per chunk and then the combine
  * (PINNED_HOST); never allocates and never synchronises the stream, so it
  * may be captured into a HIP graph (DEVICE, ZEROCOPY). */
 int agg_run(agg_plan_t plan, const void* col, int64_t n, agg_result* out, void* stream);

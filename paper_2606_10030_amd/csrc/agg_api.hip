@@ -215,9 +215,8 @@ struct agg_plan_s {
   agg_tune tune{};
   int kind = -1;
   int width = 0;
-  void* ws = nullptr;             // partial slots + completion counter
+  void* ws = nullptr;             // segment partial slots
   uint64_t* part = nullptr;
-  unsigned int* ticket = nullptr;
   // pinned-host staging
   int depth = 0;
   int64_t stage_bytes = 0;
@@ -289,10 +288,9 @@ int alloc_device(void** p, size_t bytes) {
   } while (0)
 
 int plan_create(agg_plan_s* p) {
-  const size_t ws_bytes = (size_t)kSegTarget * 8 + 256;
+  const size_t ws_bytes = (size_t)kSegTarget * 8;
   RET_IF(alloc_device(&p->ws, ws_bytes));
   p->part = static_cast<uint64_t*>(p->ws);
-  p->ticket = reinterpret_cast<unsigned int*>(static_cast<char*>(p->ws) + (size_t)kSegTarget * 8);
   HIPCHK(hipMemset(p->ws, 0, ws_bytes));
   if (p->src == AGG_SRC_PINNED_HOST) {
     agg_shape s;
@@ -446,22 +444,28 @@ int agg_run(agg_plan_t p, const void* col, int64_t n, agg_result* out, void* str
   ScanArgs a;
   a.col_bytes = bytes;
   a.seg_bytes = s.seg_bytes;
-  a.nseg = s.nseg;
   a.part = p->part;
-  a.ticket = p->ticket;
-  a.out = out;
-  a.n = n;
-  a.is_avg = p->op == AGG_AVG;
-  a.prec_used = is_float_sum ? p->prec : -1;
+  CombineArgs c;
+  c.part = p->part;
+  c.nseg = s.nseg;
+  c.out = out;
+  c.n = n;
+  c.is_avg = p->op == AGG_AVG;
+  c.prec_used = is_float_sum ? p->prec : -1;
+  const void* combine_fn = combine_kernel_ptr(p->kind);
+  if (!combine_fn) return AGG_E_INVALID;
 
   if (p->src != AGG_SRC_PINNED_HOST || n == 0) {
-    const void* fn = scan_kernel_ptr(p->kind, t.unroll, t.nontemporal != 0, aligned || n == 0);
-    if (!fn) return AGG_E_INVALID;
-    a.base = static_cast<const char*>(col);
-    a.seg_lo = 0;
-    a.seg_hi = s.nseg;
-    a.base_seg = 0;
-    return launch(fn, grid_for(t, cu, s.nseg), 64 * t.waves_per_block, &a, stream);
+    if (s.nseg > 0) {
+      const void* fn = scan_kernel_ptr(p->kind, t.unroll, t.nontemporal != 0, aligned);
+      if (!fn) return AGG_E_INVALID;
+      a.base = static_cast<const char*>(col);
+      a.seg_lo = 0;
+      a.seg_hi = s.nseg;
+      a.base_seg = 0;
+      RET_IF(launch(fn, grid_for(t, cu, s.nseg), 64 * t.waves_per_block, &a, stream));
+    }
+    return launch(combine_fn, 1, kCombineThreads, &c, stream);
   }
 
   // Pinned host: copy chunks of whole segments into the staging ring on the
@@ -473,9 +477,9 @@ int agg_run(agg_plan_t p, const void* col, int64_t n, agg_result* out, void* str
   const char* host = static_cast<const char*>(col);
   HIPCHK(hipEventRecord(p->start, stream));
   HIPCHK(hipStreamWaitEvent(p->copy_stream, p->start, 0));
-  for (int64_t c = 0; c < nchunks; ++c) {
-    const int slot = (int)(c % p->depth);
-    const int64_t lo = c * cs, hi = std::min(s.nseg, lo + cs);
+  for (int64_t k = 0; k < nchunks; ++k) {
+    const int slot = (int)(k % p->depth);
+    const int64_t lo = k * cs, hi = std::min(s.nseg, lo + cs);
     const int64_t b0 = lo * s.seg_bytes;
     const int64_t nb = std::min(bytes, hi * s.seg_bytes) - b0;
     if (p->slot_used[slot]) HIPCHK(hipStreamWaitEvent(p->copy_stream, p->consumed[slot], 0));
@@ -490,7 +494,7 @@ int agg_run(agg_plan_t p, const void* col, int64_t n, agg_result* out, void* str
     HIPCHK(hipEventRecord(p->consumed[slot], stream));
     p->slot_used[slot] = true;
   }
-  return AGG_OK;
+  return launch(combine_fn, 1, kCombineThreads, &c, stream);
 }
 
 int agg_plan_destroy(agg_plan_t plan) {

@@ -25,9 +25,13 @@ struct ScanArgs {
   int64_t seg_bytes;     // canonical segment size
   int64_t seg_lo, seg_hi;
   int64_t base_seg;      // segment index that `base` points at
-  int64_t nseg;          // segments of the whole column
-  void* part;            // nseg segment partials (8-byte slots)
-  unsigned int* ticket;  // segments completed so far; reset to 0 by the combiner
+  void* part;            // segment partials (8-byte slots), indexed by segment
+};
+
+// The single-column merge of all segment partials.
+struct CombineArgs {
+  const void* part;
+  int64_t nseg;
   agg_result* out;
   int64_t n;
   int32_t is_avg;
@@ -74,10 +78,12 @@ bool tune_cache_lookup(int kind, int32_t src, int64_t bytes, agg_tune* out);
 void builtin_tune_for(int kind, agg_tune* out);
 
 const void* scan_kernel_ptr(int kind, int unroll, bool nontemporal, bool aligned);
+const void* combine_kernel_ptr(int kind);
 const void* batch_scan_kernel_ptr(int unroll, bool nontemporal);
 const void* batch_combine_kernel_ptr();
 
 constexpr int64_t kSegMin = 16 * 1024;
+constexpr int kCombineThreads = 256;   // workgroup of the combine kernels
 constexpr int64_t kSegTarget = 8192;   // at most this many segments per column
 
 }  // namespace agg

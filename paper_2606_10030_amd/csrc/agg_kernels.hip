@@ -1,14 +1,14 @@
 // Kernels of the aggregation scan for gfx950.
 //
-// scan_kernel: the single-column scan (paper Section 3.2, GPU specialisation,
-// rebuilt for CDNA4).  Each wave folds whole segments of the column (see
-// fold_segment) and stores one partial per segment; when a workgroup has
-// finished its segments it adds their number to a completion counter, and
-// the workgroup that completes the column merges all segment partials in the
-// canonical order and writes the result.  One launch per column, no second
-// kernel, no atomics on data values: the merge order is fixed, so the result
-// is deterministic (the property the paper's FPGA design gets from its
-// static reduction tree).
+// scan_kernel + combine_kernel: the single-column scan (paper Section 3.2,
+// GPU specialisation, rebuilt for CDNA4) as a deterministic two-pass
+// reduction.  Pass 1: each wave folds whole segments of the column (see
+// fold_segment) and stores one partial per segment.  Pass 2: one workgroup
+// merges the segment partials in the canonical order and writes the result.
+// No atomics and no fences: the merge order is fixed, so the result is
+// deterministic (the property the paper's FPGA design gets from its static
+// reduction tree), and the launch boundary is the global synchronisation the
+// paper's fused kernel takes from cooperative groups.
 //
 // batch_scan_kernel / batch_combine_kernel: many columns of mixed type and
 // function in one persistent launch; the same segment fold and the same
@@ -32,7 +32,6 @@ __global__ void __launch_bounds__(1024) scan_kernel(ScanArgs a) {
   // the whole segment loop and its addresses) in scalar registers.
   const int64_t wave = (int64_t)blockIdx.x * W + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   P* part = reinterpret_cast<P*>(a.part);
-
   for (int64_t j = a.seg_lo + wave; j < a.seg_hi; j += nwaves) {
     const int64_t begin = j * a.seg_bytes;
     const int64_t valid = a.col_bytes - begin < a.seg_bytes ? a.col_bytes - begin : a.seg_bytes;
@@ -41,35 +40,16 @@ __global__ void __launch_bounds__(1024) scan_kernel(ScanArgs a) {
     acc = wave_reduce(acc, AccMerge<K>());
     if (lane == 0) part[j] = F::to_part(acc);
   }
+}
 
-  // Completion: release this workgroup's partials, count its segments.
-  __threadfence();
-  __syncthreads();
-  __shared__ int s_last;
-  if (threadIdx.x == 0) {
-    const int64_t span = a.seg_hi - a.seg_lo;
-    int64_t mine = 0;
-    for (int w = 0; w < W; ++w) {
-      const int64_t p = (int64_t)blockIdx.x * W + w;
-      if (p < span) mine += (span - p + nwaves - 1) / nwaves;
-    }
-    int last = 0;
-    if (mine > 0) {
-      const unsigned old = atomicAdd(a.ticket, (unsigned)mine);
-      last = (int64_t)old + mine == a.nseg;
-    } else if (a.nseg == 0 && blockIdx.x == 0) {
-      last = 1;  // empty column: nothing to wait for
-    }
-    s_last = last;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();  // acquire every other workgroup's partials
-  const P total = combine_partials<K>(part, a.nseg);
-  if (threadIdx.x == 0) {
-    *a.out = finalize<K>(total, a.n, a.is_avg != 0, a.prec_used);
-    *a.ticket = 0;
-  }
+// Second pass: one workgroup merges the nseg segment partials in the
+// canonical order and writes the result.  The kernel boundary after the
+// scan launches is the global synchronisation: no fences, no atomics.
+template <int K>
+__global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
+  using P = typename Fold<K>::part;
+  const P total = combine_partials<K>(reinterpret_cast<const P*>(a.part), a.nseg);
+  if (threadIdx.x == 0) *a.out = finalize<K>(total, a.n, a.is_avg != 0, a.prec_used);
 }
 
 // ------------------------------------------------------------ batch
@@ -183,6 +163,20 @@ const void* scan_kernel_ptr(int kind, int unroll, bool nontemporal, bool aligned
   const int ui = unroll_index(unroll);
   if (kind < 0 || kind >= K_NUM || ui < 0) return nullptr;
   return scan_lookup(kind, ui, nontemporal, aligned, std::make_integer_sequence<int, K_NUM>());
+}
+
+namespace {
+template <int... Ks>
+const void* combine_lookup(int kind, std::integer_sequence<int, Ks...>) {
+  const void* r = nullptr;
+  ((kind == Ks ? (r = reinterpret_cast<const void*>(&combine_kernel<Ks>), 0) : 0), ...);
+  return r;
+}
+}  // namespace
+
+const void* combine_kernel_ptr(int kind) {
+  if (kind < 0 || kind >= K_NUM) return nullptr;
+  return combine_lookup(kind, std::make_integer_sequence<int, K_NUM>());
 }
 
 const void* batch_scan_kernel_ptr(int unroll, bool nontemporal) {
