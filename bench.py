@@ -94,6 +94,125 @@ def counters_mode(n: int):
     log("counters mode done")
 
 
+def bench_batch(agg, torch, stream, table):
+    """4096 columns, lengths log-uniform in [1e3, 1e7], dtype uniform over int32 /
+    int64 / float32, function uniform over SUM / MIN / MAX / AVG (seed 12); also
+    the same columns rescaled to 2^30 items in total."""
+    import numpy as np
+    import datagen
+    r = np.random.default_rng(12)
+    ncols = 4096
+    lens = np.floor(np.exp(r.uniform(np.log(1e3), np.log(1e7), ncols))).astype(np.int64)
+    dts = [DTYPES[i] for i in r.integers(0, 3, ncols)]
+    ops = [["sum", "min", "max", "avg"][i] for i in r.integers(0, 4, ncols)]
+    out = {}
+    for label, scale in (("log_uniform_1e3_1e7", 1.0), ("rescaled_to_2^30_items", None)):
+        ln = lens if scale else np.maximum(1, np.floor(lens * (N_ITEMS / lens.sum()))).astype(np.int64)
+        tdt = {"i32": torch.int32, "i64": torch.int64, "f32": torch.float32}
+        # one device buffer per dtype, columns at 256-byte aligned offsets
+        offs, tot = [], {d: 0 for d in DTYPES}
+        for dt, n in zip(dts, ln):
+            offs.append(tot[dt])
+            tot[dt] += -(-int(n) * WIDTH[dt] // 256) * 256 // WIDTH[dt]
+        bufs = {d: torch.empty(max(1, tot[d]), dtype=tdt[d], device="cuda") for d in DTYPES}
+        stage = torch.empty(int(ln.max()) * 8, dtype=torch.uint8, pin_memory=True)
+        t0 = time.time()
+        for i, (dt, n) in enumerate(zip(dts, ln)):
+            datagen.fill_ptr(stage.data_ptr(), int(n), dt, "uniform", 1000 + i)
+            dst = bufs[dt][offs[i]:offs[i] + int(n)]
+            dst.view(torch.uint8).copy_(stage[:int(n) * WIDTH[dt]], non_blocking=False)
+        log(f"batch columns ({label}) generated in {time.time() - t0:.1f}s")
+        cols = [agg.BatchColumn(bufs[dt][offs[i]:offs[i] + int(n)], ops[i]) for i, (dt, n) in enumerate(zip(dts, ln))]
+        total_bytes = int(sum(int(n) * WIDTH[dt] for dt, n in zip(dts, ln)))
+        b = agg.Batch(cols)
+        tuned, tuned_ms = b.autotune(stream)
+        res = torch.zeros(ncols * 32, dtype=torch.uint8, device="cuda")
+        for _ in range(2):
+            b.enqueue(res, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            b.enqueue(res, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        # the same columns as 4096 separate agg_run calls
+        plans = {}
+        for c, dt in zip(cols, dts):
+            key = (dt, c.op)
+            if key not in plans:
+                plans[key] = agg.Plan(dt, c.op, max_n=int(ln.max()))
+        o = torch.zeros(32, dtype=torch.uint8, device="cuda")
+        for c, dt in zip(cols, dts):
+            plans[(dt, c.op)].enqueue(c.col, o, stream=stream)
+        e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e2.record(stream)
+        for c, dt in zip(cols, dts):
+            plans[(dt, c.op)].enqueue(c.col, o, stream=stream)
+        e3.record(stream)
+        torch.cuda.synchronize()
+        ms_sep = e2.elapsed_time(e3)
+        gbs = total_bytes / (ms * 1e-3) / 1e9
+        out[label] = {"columns": ncols, "items": int(ln.sum()), "bytes": total_bytes, "graph_ms": round(ms, 3),
+                      "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                      "separate_agg_run_ms": round(ms_sep, 3),
+                      "separate_GB/s": round(total_bytes / (ms_sep * 1e-3) / 1e9, 1),
+                      "tuned": {"unroll": tuned.unroll, "waves_per_block": tuned.waves_per_block,
+                                "blocks_per_cu": tuned.blocks_per_cu},
+                      "work_items": b.info()["nitems"],
+                      "plain_single_column_i32_sum_GB/s": table["i32_sum"]["GB/s"]}
+        for p in plans.values():
+            p.close()
+        b.close()
+        del bufs, cols, stage
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_serve(agg, torch, host_i32, dev_i32, full=False):
+    """Poisson stream of int32 requests, lengths log-uniform in [1e4, n_max],
+    30% resident (slices of a column in HBM) and 70% shipped from pinned host
+    memory, admitted by a 200 GB HBM budget, at 0.8 of the PCIe-bound capacity."""
+    from datagen.serving import mean_bytes, request_stream
+    nreq, n_max = (10_000, 1 << 33) if full else (1000, 1 << 30)
+    arena_h = host_i32
+    if full:
+        arena_h = torch.empty(n_max, dtype=torch.int32, pin_memory=True)
+        import datagen
+        datagen.fill_ptr(arena_h.data_ptr(), n_max, "i32", "uniform", 13)
+    cap = 55e9 / (0.7 * mean_bytes(10_000, n_max, 4))
+    rate = 0.8 * cap
+    specs = request_stream(nreq, seed=13, n_min=10_000, n_max=n_max, rate_per_s=rate, resident_frac=0.3,
+                           hot_items=dev_i32.numel(), arena_items=arena_h.numel())
+    reqs = [dict(ptr=(dev_i32 if s["resident"] else arena_h).data_ptr() + 4 * s["offset"], n=s["n"],
+                 column_id=s["column_id"], arrival_s=s["arrival_s"], dtype="i32", op=s["op"],
+                 resident=s["resident"]) for s in specs]
+    budget = 200 * 10**9
+    free, _ = torch.cuda.mem_get_info()
+    budget = min(budget, int(free - (8 << 30)))
+    srv = agg.Server(hbm_budget_bytes=budget, max_slots=8, cache_shipped=False)
+    t0 = time.time()
+    results, stats, sm = srv.run(reqs)
+    wall = time.time() - t0
+    srv.close()
+    lat = [s["done_s"] - s["arrival_s"] for s in stats]
+    lat_res = [s["done_s"] - s["arrival_s"] for s, q in zip(stats, reqs) if q["resident"]]
+    lat_ship = [s["done_s"] - s["arrival_s"] for s, q in zip(stats, reqs) if not q["resident"]]
+    return {"requests": nreq, "n_range": [10_000, n_max], "arrival_rate_per_s": round(rate, 1),
+            "hbm_budget_bytes": budget, "max_slots": 8,
+            "completed": sm["completed"], "failed": sm["failed"],
+            "p50_ms": round(agg.percentile(lat, 50) * 1e3, 3), "p99_ms": round(agg.percentile(lat, 99) * 1e3, 3),
+            "resident_p50_ms": round(agg.percentile(lat_res, 50) * 1e3, 3),
+            "resident_p99_ms": round(agg.percentile(lat_res, 99) * 1e3, 3),
+            "shipped_p50_ms": round(agg.percentile(lat_ship, 50) * 1e3, 3),
+            "shipped_p99_ms": round(agg.percentile(lat_ship, 99) * 1e3, 3),
+            "makespan_s": round(sm["makespan_s"], 3), "wall_s": round(wall, 3),
+            "scanned_GB/s": round(sm["bytes_scanned"] / sm["makespan_s"] / 1e9, 2),
+            "shipped_GB/s": round(sm["bytes_shipped"] / sm["makespan_s"] / 1e9, 2),
+            "bytes_scanned": sm["bytes_scanned"], "bytes_shipped": sm["bytes_shipped"],
+            "peak_busy_slots": sm["peak_busy_slots"], "peak_reserved_bytes": sm["peak_reserved_bytes"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +220,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-e2e", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving with 10^4 requests of up to 2^33 int32 items (minutes of PCIe time)")
     ap.add_argument("--n", type=int, default=N_ITEMS, help=argparse.SUPPRESS)
     ap.add_argument("--counters", action="store_true",
                     help="profiling mode for rocprofv3 --pmc: a 1 GiB device copy (calibration) "
@@ -262,6 +385,14 @@ def main():
         e2e_ms = n * 4 / (e2e["pinned_host_i32_sum"]["GB/s"] * 1e9) * 1e3
         e2e["transfer_share_of_e2e_time"] = round(1 - dev_ms / e2e_ms, 4)
         extra["e2e"] = e2e
+
+    # ---- batch: 4096 mixed columns in one persistent launch under a HIP graph
+    if not args.no_batch:
+        extra["batch"] = bench_batch(agg, torch, stream, table)
+
+    # ---- serving: Poisson requests, 30% resident / 70% shipped, HBM budget
+    if not args.no_serve:
+        extra["serve"] = bench_serve(agg, torch, host["i32"], dev["i32"], full=args.serve_full)
 
     # ---- CPU oracle baseline (rank 0, N = 1): one step's cells on the host cores
     cpu = None

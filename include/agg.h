@@ -215,6 +215,80 @@ int agg_tune_save(const char* path);
 int agg_tune_load(const char* path);
 int agg_tune_clear(void);
 
+/* ---- serving: continuous admission of requests (agg_serve) ---- */
+
+typedef struct agg_server_s* agg_server_t;
+
+/* One aggregation request.  Requests passed to agg_serve_run are sorted by
+ * arrival_s.  A resident request reads device memory; a shipped one reads
+ * page-locked host memory, which the server copies over PCIe into its HBM
+ * arena.  Requests with the same column_id must name the same bytes. */
+typedef struct agg_request {
+    const void* ptr;     /* item 0: device address (resident) or pinned host address (shipped) */
+    int64_t n;           /* items */
+    int64_t column_id;   /* identity of the column's contents (for the resident cache) */
+    double arrival_s;    /* seconds after agg_serve_run starts */
+    int32_t dtype, op, prec;
+    int32_t resident;    /* 1: ptr is device memory; 0: ship from pinned host memory */
+} agg_request;
+
+typedef struct agg_serve_config {
+    int64_t hbm_budget_bytes;  /* device arena for shipped (and cached) columns */
+    int32_t max_slots;         /* requests in flight on the GPU, 1..64; each slot owns
+                                  a compute stream and a copy stream */
+    int32_t cache_shipped;     /* 1: a shipped column stays in the arena after its request
+                                  (LRU eviction by need), serving later requests with the
+                                  same column_id without PCIe traffic */
+    int64_t chunk_bytes;       /* copy / scan pipelining chunk for shipped columns */
+} agg_serve_config;
+
+typedef struct agg_request_stats {
+    double arrival_s;      /* as requested */
+    double admit_s;        /* when the scheduler gave it a slot (and memory) */
+    double done_s;         /* when the host saw its result */
+    int64_t bytes_shipped; /* bytes copied over PCIe for it */
+    int32_t slot;          /* slot it ran in, -1 if never admitted */
+    int32_t status;        /* AGG_OK; AGG_E_NOMEM if the column exceeds the whole budget */
+    int32_t cache_hit;     /* 1: served from a cached copy */
+    int32_t reserved;
+} agg_request_stats;
+
+typedef struct agg_serve_summary {
+    double makespan_s;            /* first arrival to last completion */
+    int64_t bytes_scanned;
+    int64_t bytes_shipped;
+    int64_t peak_reserved_bytes;  /* high-water mark of the arena (<= the budget) */
+    int32_t peak_busy_slots;      /* most requests in flight at once */
+    int32_t completed, failed, cache_hits;
+} agg_serve_summary;
+
+/* Create a server: allocates the hbm_budget_bytes arena, per-slot streams,
+ * events and partial workspaces, and page-locked result slots. */
+int agg_serve_create(agg_server_t* out, const agg_serve_config* cfg);
+
+/* Serve reqs[0..n) in real time on the current device.  The scheduler
+ * releases each request at its arrival time, admits waiting requests in
+ * arrival order whenever a slot is free and, for a shipped request, the
+ * arena has room (evicting idle cached columns in LRU order); a shipped
+ * request that does not fit holds back later shipped requests but not
+ * resident or cached ones.  Each admitted request runs the agg_run kernels
+ * (same canonical shape, hence the same bits as alone) on its slot's
+ * streams, copies of shipped chunks overlapping the scan of earlier chunks.
+ * Fills results[i] (host memory) and stats[i]; returns when all are done.
+ * Pointers are validated up front (AGG_E_INVALID before any work). */
+int agg_serve_run(agg_server_t server, const agg_request* reqs, int32_t n, agg_result* results,
+                  agg_request_stats* stats, agg_serve_summary* summary);
+
+int agg_serve_destroy(agg_server_t server);
+
+/* The same scheduler on the CPU with a simulated clock: copies share one
+ * link of pcie_gbs GB/s, scans run at hbm_gbs GB/s, each request adds
+ * launch_s seconds.  No device is touched; for testing the admission,
+ * budget and cache logic. */
+int agg_serve_simulate(const agg_serve_config* cfg, const agg_request* reqs, int32_t n, double pcie_gbs,
+                       double hbm_gbs, double launch_s, agg_request_stats* stats,
+                       agg_serve_summary* summary);
+
 /* ---- errors ---- */
 const char* agg_strerror(int32_t code);
 int32_t agg_last_hip_error(void);  /* hipError_t of the last AGG_E_HIP on this thread */

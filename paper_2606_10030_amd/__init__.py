@@ -68,6 +68,34 @@ class Col(ctypes.Structure):
                 ("op", ctypes.c_int32), ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("n", ctypes.c_int64), ("column_id", ctypes.c_int64),
+                ("arrival_s", ctypes.c_double), ("dtype", ctypes.c_int32), ("op", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("resident", ctypes.c_int32)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("cache_shipped", ctypes.c_int32), ("chunk_bytes", ctypes.c_int64)]
+
+
+class RequestStats(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("bytes_shipped", ctypes.c_int64), ("slot", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("cache_hit", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ServeSummary(ctypes.Structure):
+    _fields_ = [("makespan_s", ctypes.c_double), ("bytes_scanned", ctypes.c_int64),
+                ("bytes_shipped", ctypes.c_int64), ("peak_reserved_bytes", ctypes.c_int64),
+                ("peak_busy_slots", ctypes.c_int32), ("completed", ctypes.c_int32),
+                ("failed", ctypes.c_int32), ("cache_hits", ctypes.c_int32)]
+
+
+def _struct_dict(x) -> dict:
+    return {f: getattr(x, f) for f, _ in x._fields_ if f != "reserved"}
+
+
 RESULT_BYTES = ctypes.sizeof(Result)
 assert RESULT_BYTES == 32
 
@@ -111,6 +139,13 @@ def lib():
         "agg_tune_save": ([ctypes.c_char_p], ctypes.c_int),
         "agg_tune_load": ([ctypes.c_char_p], ctypes.c_int),
         "agg_tune_clear": ([], ctypes.c_int),
+        "agg_serve_create": ([ctypes.POINTER(vp), ctypes.POINTER(ServeConfig)], ctypes.c_int),
+        "agg_serve_run": ([vp, ctypes.POINTER(Request), i32, vp, ctypes.POINTER(RequestStats),
+                           ctypes.POINTER(ServeSummary)], ctypes.c_int),
+        "agg_serve_destroy": ([vp], ctypes.c_int),
+        "agg_serve_simulate": ([ctypes.POINTER(ServeConfig), ctypes.POINTER(Request), i32, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, ctypes.POINTER(RequestStats),
+                                ctypes.POINTER(ServeSummary)], ctypes.c_int),
         "agg_strerror": ([i32], ctypes.c_char_p),
         "agg_last_hip_error": ([], i32),
     }
@@ -377,3 +412,79 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ serving
+def _requests(reqs) -> "ctypes.Array":
+    """Requests from dicts: ptr (int address or tensor), n, column_id, arrival_s,
+    dtype, op, prec (default neumaier), resident (bool)."""
+    arr = (Request * max(1, len(reqs)))()
+    for i, r in enumerate(reqs):
+        col = r["ptr"]
+        ptr = col if isinstance(col, int) else col.data_ptr()
+        n = r["n"] if "n" in r else col.numel()
+        arr[i] = Request(ptr, int(n), int(r.get("column_id", i)), float(r["arrival_s"]),
+                         _code(r["dtype"], DTYPES, "dtype"), _code(r["op"], OPS, "op"),
+                         _code(r.get("prec", "neumaier"), PRECS, "prec"), 1 if r.get("resident") else 0)
+    return arr
+
+
+def _config(hbm_budget_bytes, max_slots, cache_shipped, chunk_bytes) -> ServeConfig:
+    return ServeConfig(int(hbm_budget_bytes), int(max_slots), 1 if cache_shipped else 0, int(chunk_bytes))
+
+
+class Server:
+    """agg_serve_create / agg_serve_run: continuous admission of requests on the GPU."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, cache_shipped: bool = True,
+                 chunk_bytes: int = 64 << 20):
+        self.cfg = _config(hbm_budget_bytes, max_slots, cache_shipped, chunk_bytes)
+        h = ctypes.c_void_p()
+        _check(lib().agg_serve_create(ctypes.byref(h), ctypes.byref(self.cfg)), "agg_serve_create")
+        self._h = h
+
+    def run(self, reqs: list):
+        """Serve the requests (sorted by arrival_s); returns (results, stats, summary)."""
+        arr = _requests(reqs)
+        n = len(reqs)
+        res = (Result * max(1, n))()
+        st = (RequestStats * max(1, n))()
+        sm = ServeSummary()
+        _check(lib().agg_serve_run(self._h, arr, n, ctypes.cast(res, ctypes.c_void_p), st, ctypes.byref(sm)),
+               "agg_serve_run")
+        results = [result_dict(res[i], arr[i].dtype, arr[i].op) for i in range(n)]
+        return results, [_struct_dict(st[i]) for i in range(n)], _struct_dict(sm)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().agg_serve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def serve_simulate(reqs: list, hbm_budget_bytes: int, max_slots: int = 8, cache_shipped: bool = True,
+                   chunk_bytes: int = 64 << 20, pcie_gbs: float = 55.0, hbm_gbs: float = 7000.0,
+                   launch_s: float = 10e-6):
+    """The serving scheduler on the CPU with a simulated clock (no device)."""
+    cfg = _config(hbm_budget_bytes, max_slots, cache_shipped, chunk_bytes)
+    arr = _requests(reqs)
+    n = len(reqs)
+    st = (RequestStats * max(1, n))()
+    sm = ServeSummary()
+    _check(lib().agg_serve_simulate(ctypes.byref(cfg), arr, n, pcie_gbs, hbm_gbs, launch_s, st, ctypes.byref(sm)),
+           "agg_serve_simulate")
+    return [_struct_dict(st[i]) for i in range(n)], _struct_dict(sm)
+
+
+def percentile(xs, q: float) -> float:
+    """Nearest-rank percentile (q in [0, 100])."""
+    v = sorted(xs)
+    if not v:
+        return float("nan")
+    k = max(0, min(len(v) - 1, int(-(-q * len(v) // 100)) - 1))
+    return v[k]

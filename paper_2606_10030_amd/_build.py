@@ -1,16 +1,21 @@
-"""Build libagg.so (the HIP library) in-tree for gfx950 with hipcc."""
+"""Build libagg.so (the HIP library) in-tree for gfx950 with hipcc.
+
+Each source compiles to an object in `_build/` in parallel, then one link
+produces `libagg.so` next to this file."""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
+OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libagg.so")
-SOURCES = ["agg_kernels.hip", "agg_api.hip", "agg_tuner.hip"]
+SOURCES = ["agg_kernels.hip", "agg_api.hip", "agg_tuner.hip", "agg_serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -18,7 +23,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-ffp-contract=off",       # no fused multiply-add contraction anywhere
     "-fno-fast-math",
     "-Wall",
@@ -26,23 +30,33 @@ FLAGS = [
     # packed FP32 instructions stay off (v_pk_add_f32 and friends)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
+# hipcc's host pass does not know the packed-fp32 feature; that note is harmless.
+_NOISE = "'-packed-fp32-ops' is not a recognized feature for this target"
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into libagg.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
-    # hipcc's host pass does not know the packed-fp32 feature; that note is harmless.
-    noise = "'-packed-fp32-ops' is not a recognized feature for this target"
-    err = "\n".join(l for l in res.stderr.splitlines() if noise not in l)
+    err = "\n".join(l for l in res.stderr.splitlines() if _NOISE not in l)
     if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{err}")
+        raise RuntimeError(f"hipcc failed ({res.returncode}): {' '.join(cmd)}\n{err}")
     if err.strip() and verbose:
         print(err, file=sys.stderr)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source and link libagg.so (always recompiles)."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    objs = [os.path.join(OBJDIR, s.replace(".hip", ".o")) for s in SOURCES]
+    cmds = [[HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, s), "-o", o]
+            for s, o in zip(SOURCES, objs)]
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -52,9 +52,10 @@ int unroll_index(int32_t unroll) {
 
 using namespace agg;
 
-namespace {
+namespace agg {
 
 thread_local int32_t g_last_hip = 0;
+void record_hip_error(int32_t e) { g_last_hip = e; }
 
 #define HIPCHK(expr)                                  \
   do {                                                \
@@ -103,6 +104,8 @@ int device_check(int dev) {
   return d.status;
 }
 
+int device_cu(int dev) { return (dev >= 0 && dev < kMaxDevices) ? g_dev[dev].cu : 0; }
+
 int current_device(int* dev) {
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
@@ -113,17 +116,13 @@ int current_device(int* dev) {
   return device_check(*dev);
 }
 
-}  // namespace
-
-bool agg::tune_is_valid(const agg_tune& t) {
+bool tune_is_valid(const agg_tune& t) {
   const int w = t.waves_per_block;
   return (w == 1 || w == 2 || w == 4 || w == 8 || w == 16) &&
          t.blocks_per_cu >= 1 && t.blocks_per_cu <= 32 && unroll_index(t.unroll) >= 0 &&
          (t.nontemporal == 0 || t.nontemporal == 1) && t.chunk_bytes >= (1 << 20) &&
          t.chunk_bytes <= ((int64_t)1 << 32) && t.staging_depth >= 2 && t.staging_depth <= 4;
 }
-
-namespace {
 
 bool valid_tune(const agg_tune& t) { return tune_is_valid(t); }
 
@@ -205,7 +204,7 @@ int launch(const void* fn, int grid, int block, void* args, hipStream_t stream) 
   return AGG_OK;
 }
 
-}  // namespace
+}  // namespace agg
 
 struct agg_plan_s {
   int device = 0;

@@ -2,6 +2,7 @@
 // runtime (agg_api.hip).  Not part of the public ABI.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "agg.h"
@@ -72,6 +73,18 @@ struct BatchArgs {
 int kind_of(int32_t dtype, int32_t op, int32_t prec);  // -1 if invalid
 int width_of(int32_t dtype);                          // 4 or 8, 0 if invalid
 int unroll_index(int32_t unroll);                      // 0..3 for 4,8,16,32; -1 otherwise
+
+// Host helpers shared by the runtime files.
+void record_hip_error(int32_t e);                 // remembered for agg_last_hip_error
+int current_device(int* dev);                     // current HIP device, checked to be gfx950
+int device_cu(int dev);                           // its compute-unit count
+void shape_of(int32_t dtype, int64_t n, agg_shape* s);
+void tune_for(int kind, int32_t src, int64_t bytes, agg_tune* t);
+int check_pointer(const void* p, int64_t bytes, int32_t src, int dev);
+int check_out_pointer(const void* p, int64_t bytes, int dev);
+int grid_for(const agg_tune& t, int cu, int64_t nseg);
+int launch(const void* fn, int grid, int block, void* args, hipStream_t stream);
+int64_t ceil_div(int64_t a, int64_t b);
 
 bool tune_is_valid(const agg_tune& t);
 bool tune_cache_lookup(int kind, int32_t src, int64_t bytes, agg_tune* out);

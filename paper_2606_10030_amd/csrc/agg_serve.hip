@@ -1,0 +1,574 @@
+// Serving: continuous admission of aggregation requests on one GPU.
+//
+// Requests arrive over time (Poisson in the benchmark workload).  The
+// scheduler admits them in arrival order into a fixed number of slots as
+// slots and HBM free up; a slot owns a compute stream and a copy stream, so
+// the work of admitted requests overlaps on the device.  A resident request
+// scans a column already in HBM.  A shipped request reserves room for its
+// column in a device arena of `hbm_budget_bytes`, copies it over PCIe in
+// chunks while the scan of earlier chunks runs (the paper's end-to-end
+// setting, Section 5.3), and may stay resident afterwards in an LRU cache
+// keyed by column id, so later requests for the same column skip the copy.
+//
+// Every request runs the same kernels and canonical reduction shape as
+// agg_run, so its result is bit-identical alone and in any mix.
+//
+// The scheduler is plain host logic behind an executor interface: the HIP
+// executor runs requests on the GPU; a simulated executor (modelled PCIe and
+// HBM rates, simulated clock) drives the same scheduler on the CPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <limits>
+#include <map>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "agg.h"
+#include "agg_internal.hpp"
+
+namespace agg {
+namespace serve {
+
+constexpr int kMaxSlots = 64;
+constexpr int64_t kGranule = 256;
+
+int64_t round_up(int64_t b) { return (b + kGranule - 1) / kGranule * kGranule; }
+
+// First-fit allocator over the device arena [0, capacity).
+class Arena {
+ public:
+  explicit Arena(int64_t cap) : cap_(cap) {
+    if (cap > 0) free_[0] = cap;
+  }
+  bool alloc(int64_t bytes, int64_t* off) {
+    bytes = round_up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const int64_t rest = it->second - bytes, noff = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[noff] = rest;
+      used_ += bytes;
+      peak_ = std::max(peak_, used_);
+      return true;
+    }
+    return false;
+  }
+  void release(int64_t off, int64_t bytes) {
+    bytes = round_up(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  int64_t capacity() const { return cap_; }
+  int64_t peak() const { return peak_; }
+
+ private:
+  int64_t cap_ = 0, used_ = 0, peak_ = 0;
+  std::map<int64_t, int64_t> free_;
+};
+
+// Shipped columns kept in HBM after their request, least recently used first out.
+struct CacheEntry {
+  int64_t off, bytes;
+  int users;
+  uint64_t stamp;
+};
+class Cache {
+ public:
+  CacheEntry* lookup(int64_t id, int64_t bytes) {
+    auto it = map_.find(id);
+    if (it == map_.end() || it->second.bytes != bytes) return nullptr;
+    it->second.stamp = ++clock_;
+    return &it->second;
+  }
+  // Keep (off, bytes) for id; false if id is already cached (caller frees its copy).
+  bool insert(int64_t id, int64_t off, int64_t bytes) {
+    if (map_.count(id)) return false;
+    map_[id] = CacheEntry{off, bytes, 0, ++clock_};
+    return true;
+  }
+  // Allocate `bytes`, evicting idle entries in LRU order while needed.
+  bool make_room(Arena& a, int64_t bytes, int64_t* off) {
+    while (!a.alloc(bytes, off)) {
+      auto victim = map_.end();
+      for (auto it = map_.begin(); it != map_.end(); ++it)
+        if (it->second.users == 0 && (victim == map_.end() || it->second.stamp < victim->second.stamp))
+          victim = it;
+      if (victim == map_.end()) return false;
+      a.release(victim->second.off, victim->second.bytes);
+      map_.erase(victim);
+    }
+    return true;
+  }
+
+ private:
+  std::unordered_map<int64_t, CacheEntry> map_;
+  uint64_t clock_ = 0;
+};
+
+struct Job {
+  int req = -1;
+  int kind = -1;
+  bool ship = false;        // copy the column over PCIe into the arena
+  bool from_arena = false;  // the column is read from the arena (shipped or cached)
+  bool cached = false;      // a cache hit
+  int64_t off = 0;
+  int64_t bytes = 0;
+};
+
+class Executor {
+ public:
+  virtual ~Executor() {}
+  virtual int start(int slot, const agg_request& r, const Job& j) = 0;
+  virtual int poll(int slot) = 0;  // 1 done, 0 running, < 0 error
+  virtual void finish(int slot, agg_result* out) = 0;
+  virtual double now() = 0;
+  virtual void wait(double until) = 0;
+};
+
+class Scheduler {
+ public:
+  Scheduler(const agg_serve_config& cfg, Executor& ex) : cfg_(cfg), ex_(ex), arena_(cfg.hbm_budget_bytes) {}
+
+  int run(const agg_request* reqs, int32_t n, agg_result* results, agg_request_stats* stats,
+          agg_serve_summary* sum) {
+    std::vector<Job> slot(cfg_.max_slots);
+    std::vector<bool> busy(cfg_.max_slots, false);
+    std::deque<int> pending;
+    int next = 0, finished = 0, nbusy = 0, peak_busy = 0, hits = 0, failed = 0;
+    int64_t scanned = 0, shipped = 0;
+    double first = n ? reqs[0].arrival_s : 0.0, last = 0.0;
+    for (int i = 0; i < n; ++i) {
+      std::memset(&stats[i], 0, sizeof stats[i]);
+      std::memset(&results[i], 0, sizeof results[i]);
+      stats[i].arrival_s = reqs[i].arrival_s;
+      stats[i].slot = -1;
+    }
+    while (finished < n) {
+      bool progress = false;
+      const double now = ex_.now();
+      while (next < n && reqs[next].arrival_s <= now) pending.push_back(next++);
+      // completions
+      for (int s = 0; s < cfg_.max_slots; ++s) {
+        if (!busy[s]) continue;
+        const int st = ex_.poll(s);
+        if (st == 0) continue;
+        Job& j = slot[s];
+        agg_request_stats& rs = stats[j.req];
+        if (st > 0) {
+          ex_.finish(s, &results[j.req]);
+          rs.status = AGG_OK;
+        } else {
+          rs.status = st;
+          ++failed;
+        }
+        rs.done_s = ex_.now();
+        last = std::max(last, rs.done_s);
+        release(j);
+        busy[s] = false;
+        --nbusy;
+        ++finished;
+        progress = true;
+      }
+      // admissions, in arrival order; a shipped request that does not fit
+      // blocks later shipped requests (FIFO for HBM) but not resident or
+      // cached ones, which need no memory.
+      bool memory_blocked = false;
+      for (auto it = pending.begin(); it != pending.end() && nbusy < cfg_.max_slots;) {
+        const int i = *it;
+        const agg_request& r = reqs[i];
+        Job j;
+        j.req = i;
+        j.kind = kind_of(r.dtype, r.op, r.prec);
+        j.bytes = r.n * width_of(r.dtype);
+        bool admit = false;
+        if (r.resident) {
+          admit = true;
+        } else if (CacheEntry* c = cfg_.cache_shipped ? cache_.lookup(r.column_id, j.bytes) : nullptr) {
+          j.from_arena = j.cached = true;
+          j.off = c->off;
+          c->users++;
+          admit = true;
+        } else if (round_up(j.bytes) > arena_.capacity()) {
+          stats[i].status = AGG_E_NOMEM;  // can never fit the budget
+          stats[i].admit_s = stats[i].done_s = ex_.now();
+          ++failed;
+          ++finished;
+          it = pending.erase(it);
+          progress = true;
+          continue;
+        } else if (!memory_blocked && (j.bytes == 0 || cache_.make_room(arena_, j.bytes, &j.off))) {
+          j.ship = j.bytes > 0;
+          j.from_arena = j.bytes > 0;
+          admit = true;
+        } else {
+          memory_blocked = true;
+        }
+        if (!admit) {
+          ++it;
+          continue;
+        }
+        int s = 0;
+        while (busy[s]) ++s;
+        agg_request_stats& rs = stats[i];
+        rs.admit_s = ex_.now();
+        rs.slot = s;
+        rs.cache_hit = j.cached ? 1 : 0;
+        rs.bytes_shipped = j.ship ? j.bytes : 0;
+        const int rc = ex_.start(s, r, j);
+        if (rc != AGG_OK) {
+          rs.status = rc;
+          rs.done_s = ex_.now();
+          release(j);
+          ++failed;
+          ++finished;
+        } else {
+          slot[s] = j;
+          busy[s] = true;
+          ++nbusy;
+          peak_busy = std::max(peak_busy, nbusy);
+          scanned += j.bytes;
+          shipped += rs.bytes_shipped;
+          hits += j.cached ? 1 : 0;
+        }
+        it = pending.erase(it);
+        progress = true;
+      }
+      if (!progress && finished < n) ex_.wait(next < n ? reqs[next].arrival_s : std::numeric_limits<double>::infinity());
+    }
+    sum->makespan_s = n ? last - first : 0.0;
+    sum->bytes_scanned = scanned;
+    sum->bytes_shipped = shipped;
+    sum->peak_reserved_bytes = arena_.peak();
+    sum->peak_busy_slots = peak_busy;
+    sum->completed = n - failed;
+    sum->failed = failed;
+    sum->cache_hits = hits;
+    return AGG_OK;
+  }
+
+ private:
+  void release(const Job& j) {
+    if (j.cached) {
+      if (CacheEntry* c = cache_.lookup(reqs_id(j), j.bytes)) c->users--;
+      return;
+    }
+    if (!j.ship) return;
+    if (cfg_.cache_shipped && cache_.insert(cur_ids_[j.req], j.off, j.bytes)) return;
+    arena_.release(j.off, j.bytes);
+  }
+  int64_t reqs_id(const Job& j) { return cur_ids_[j.req]; }
+
+ public:
+  std::vector<int64_t> cur_ids_;  // column id per request
+
+ private:
+  agg_serve_config cfg_;
+  Executor& ex_;
+  Arena arena_;
+  Cache cache_;
+};
+
+// ------------------------------------------------------------ GPU executor
+class HipExecutor : public Executor {
+ public:
+  explicit HipExecutor(agg_server_s* s);
+  int start(int slot, const agg_request& r, const Job& j) override;
+  int poll(int slot) override;
+  void finish(int slot, agg_result* out) override { *out = res_host_[slot]; }
+  double now() override {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
+  }
+  void wait(double until) override {
+    const double dt = until - now();
+    if (dt > 50e-6) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    else std::this_thread::yield();
+  }
+
+ private:
+  agg_server_s* s_;
+  agg_result* res_host_;
+  std::chrono::steady_clock::time_point t0_;
+};
+
+// ------------------------------------------------------------ simulated executor
+class SimExecutor : public Executor {
+ public:
+  SimExecutor(int slots, double pcie_gbs, double hbm_gbs, double launch_s)
+      : done_at_(slots, -1.0), pcie_(pcie_gbs * 1e9), hbm_(hbm_gbs * 1e9), launch_(launch_s) {}
+  int start(int slot, const agg_request& r, const Job& j) override {
+    const double scan = (double)j.bytes / hbm_;
+    double end = t_ + launch_ + scan;
+    if (j.ship) {  // one shared link; the scan of the last chunk follows the copy
+      const double begin = std::max(t_, link_free_);
+      link_free_ = begin + (double)j.bytes / pcie_;
+      end = std::max(end, link_free_ + launch_);
+    }
+    done_at_[slot] = end;
+    n_[slot] = r.n;
+    return AGG_OK;
+  }
+  int poll(int slot) override { return done_at_[slot] >= 0 && t_ >= done_at_[slot] ? 1 : 0; }
+  void finish(int slot, agg_result* out) override {
+    std::memset(out, 0, sizeof *out);
+    out->count = n_[slot];
+    out->prec_used = -1;
+    done_at_[slot] = -1.0;
+  }
+  double now() override { return t_; }
+  void wait(double until) override {
+    double next = until;
+    for (double d : done_at_)
+      if (d >= 0 && d < next) next = d;
+    if (!std::isfinite(next)) next = t_ + 1e-3;  // nothing scheduled: cannot happen with work pending
+    t_ = std::max(t_, next);
+  }
+
+ private:
+  std::vector<double> done_at_;
+  std::map<int, int64_t> n_;
+  double pcie_, hbm_, launch_;
+  double t_ = 0.0, link_free_ = 0.0;
+};
+
+int validate(const agg_serve_config* cfg, const agg_request* reqs, int32_t n, bool need_device, int dev) {
+  if (!cfg || n < 0 || (n > 0 && !reqs)) return AGG_E_INVALID;
+  if (cfg->max_slots < 1 || cfg->max_slots > kMaxSlots || cfg->hbm_budget_bytes < 0) return AGG_E_INVALID;
+  if (cfg->chunk_bytes < (1 << 20) || cfg->chunk_bytes > ((int64_t)1 << 32)) return AGG_E_INVALID;
+  for (int32_t i = 0; i < n; ++i) {
+    const agg_request& r = reqs[i];
+    if (kind_of(r.dtype, r.op, r.prec) < 0 || r.n < 0 || r.n > ((int64_t)1 << 40)) return AGG_E_INVALID;
+    if (!(r.arrival_s >= 0.0) || (i > 0 && r.arrival_s < reqs[i - 1].arrival_s)) return AGG_E_INVALID;
+    if (r.n > 0 && !r.ptr) return AGG_E_INVALID;
+    const int w = width_of(r.dtype);
+    if (r.n > 0 && reinterpret_cast<uintptr_t>(r.ptr) % (uintptr_t)w != 0) return AGG_E_INVALID;
+    if (need_device && r.n > 0) {
+      const int rc = check_pointer(r.ptr, r.n * w, r.resident ? AGG_SRC_DEVICE : AGG_SRC_PINNED_HOST, dev);
+      if (rc != AGG_OK) return rc;
+    }
+  }
+  return AGG_OK;
+}
+
+}  // namespace serve
+}  // namespace agg
+
+using namespace agg;
+using namespace agg::serve;
+
+struct agg_server_s {
+  int device = 0;
+  agg_serve_config cfg{};
+  char* arena = nullptr;  // hbm_budget_bytes of device memory
+  int slots = 0;
+  hipStream_t comp[kMaxSlots] = {};
+  hipStream_t copy[kMaxSlots] = {};
+  hipEvent_t copied[kMaxSlots] = {};
+  hipEvent_t done[kMaxSlots] = {};
+  uint64_t* part = nullptr;       // slots x kSegTarget partial slots
+  agg_result* res_host = nullptr;  // slots results, page-locked host memory
+};
+
+namespace {
+
+void server_release(agg_server_s* s) {
+  if (!s) return;
+  for (int i = 0; i < s->slots; ++i) {
+    if (s->comp[i]) (void)hipStreamDestroy(s->comp[i]);
+    if (s->copy[i]) (void)hipStreamDestroy(s->copy[i]);
+    if (s->copied[i]) (void)hipEventDestroy(s->copied[i]);
+    if (s->done[i]) (void)hipEventDestroy(s->done[i]);
+  }
+  if (s->part) (void)hipFree(s->part);
+  if (s->arena) (void)hipFree(s->arena);
+  if (s->res_host) (void)hipHostFree(s->res_host);
+  delete s;
+}
+
+}  // namespace
+
+agg::serve::HipExecutor::HipExecutor(agg_server_s* s)
+    : s_(s), res_host_(s->res_host), t0_(std::chrono::steady_clock::now()) {}
+
+int agg::serve::HipExecutor::start(int slot, const agg_request& r, const Job& j) {
+  hipStream_t comp = s_->comp[slot];
+  agg_shape sh;
+  shape_of(r.dtype, r.n, &sh);
+  agg_tune t;
+  tune_for(j.kind, AGG_SRC_DEVICE, j.bytes, &t);
+  const char* col = j.from_arena ? s_->arena + j.off : static_cast<const char*>(r.ptr);
+  const bool aligned = (reinterpret_cast<uintptr_t>(col) & 15) == 0;
+  uint64_t* part = s_->part + (size_t)slot * kSegTarget;
+  ScanArgs a;
+  a.col_bytes = j.bytes;
+  a.seg_bytes = sh.seg_bytes;
+  a.part = part;
+  a.base = col;
+  a.base_seg = 0;
+  CombineArgs c;
+  c.part = part;
+  c.nseg = sh.nseg;
+  c.out = res_host_ + slot;
+  c.n = r.n;
+  c.is_avg = r.op == AGG_AVG;
+  c.prec_used = (r.dtype == AGG_F32 && (r.op == AGG_SUM || r.op == AGG_AVG)) ? r.prec : -1;
+  const void* scan_fn = scan_kernel_ptr(j.kind, t.unroll, t.nontemporal != 0, aligned);
+  const void* comb_fn = combine_kernel_ptr(j.kind);
+  if (!scan_fn || !comb_fn) return AGG_E_INVALID;
+  const int cu = device_cu(s_->device);
+  if (sh.nseg > 0 && j.ship) {
+    // copy chunks of whole segments on the copy stream; scan each as it lands
+    const int64_t cs = std::max<int64_t>(1, s_->cfg.chunk_bytes / sh.seg_bytes);
+    const char* host = static_cast<const char*>(r.ptr);
+    char* dst = s_->arena + j.off;
+    for (int64_t lo = 0; lo < sh.nseg; lo += cs) {
+      const int64_t hi = std::min(sh.nseg, lo + cs);
+      const int64_t b0 = lo * sh.seg_bytes;
+      const int64_t nb = std::min(j.bytes, hi * sh.seg_bytes) - b0;
+      hipError_t e = hipMemcpyAsync(dst + b0, host + b0, (size_t)nb, hipMemcpyHostToDevice, s_->copy[slot]);
+      if (e == hipSuccess) e = hipEventRecord(s_->copied[slot], s_->copy[slot]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(comp, s_->copied[slot], 0);
+      if (e != hipSuccess) {
+        record_hip_error((int32_t)e);
+        return AGG_E_HIP;
+      }
+      a.seg_lo = lo;
+      a.seg_hi = hi;
+      const int rc = launch(scan_fn, grid_for(t, cu, hi - lo), 64 * t.waves_per_block, &a, comp);
+      if (rc != AGG_OK) return rc;
+    }
+  } else if (sh.nseg > 0) {
+    a.seg_lo = 0;
+    a.seg_hi = sh.nseg;
+    const int rc = launch(scan_fn, grid_for(t, cu, sh.nseg), 64 * t.waves_per_block, &a, comp);
+    if (rc != AGG_OK) return rc;
+  }
+  int rc = launch(comb_fn, 1, kCombineThreads, &c, comp);
+  if (rc != AGG_OK) return rc;
+  const hipError_t e = hipEventRecord(s_->done[slot], comp);
+  if (e != hipSuccess) {
+    record_hip_error((int32_t)e);
+    return AGG_E_HIP;
+  }
+  return AGG_OK;
+}
+
+int agg::serve::HipExecutor::poll(int slot) {
+  const hipError_t e = hipEventQuery(s_->done[slot]);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) return 0;
+  record_hip_error((int32_t)e);
+  return AGG_E_HIP;
+}
+
+extern "C" {
+
+int agg_serve_create(agg_server_t* out, const agg_serve_config* cfg) {
+  if (!out) return AGG_E_INVALID;
+  *out = nullptr;
+  const int vr = validate(cfg, nullptr, 0, false, 0);
+  if (vr != AGG_OK) return vr;
+  int dev = 0;
+  const int dr = current_device(&dev);
+  if (dr != AGG_OK) return dr;
+  agg_server_s* s = new (std::nothrow) agg_server_s();
+  if (!s) return AGG_E_NOMEM;
+  s->device = dev;
+  s->cfg = *cfg;
+  auto fail = [&](int rc) {
+    server_release(s);
+    return rc;
+  };
+  hipError_t e;
+  if (cfg->hbm_budget_bytes > 0) {
+    e = hipMalloc(reinterpret_cast<void**>(&s->arena), (size_t)cfg->hbm_budget_bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      s->arena = nullptr;
+      return fail(AGG_E_NOMEM);
+    }
+  }
+  if ((e = hipMalloc(reinterpret_cast<void**>(&s->part), (size_t)cfg->max_slots * kSegTarget * 8)) != hipSuccess) {
+    (void)hipGetLastError();
+    s->part = nullptr;
+    return fail(AGG_E_NOMEM);
+  }
+  if ((e = hipHostMalloc(reinterpret_cast<void**>(&s->res_host), sizeof(agg_result) * cfg->max_slots,
+                         hipHostMallocDefault)) != hipSuccess) {
+    (void)hipGetLastError();
+    s->res_host = nullptr;
+    return fail(AGG_E_NOMEM);
+  }
+  for (int i = 0; i < cfg->max_slots; ++i) {
+    s->slots = i + 1;
+    if ((e = hipStreamCreateWithFlags(&s->comp[i], hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&s->copy[i], hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s->copied[i], hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s->done[i], hipEventDisableTiming)) != hipSuccess) {
+      record_hip_error((int32_t)e);
+      return fail(AGG_E_HIP);
+    }
+  }
+  if ((e = hipDeviceSynchronize()) != hipSuccess) {
+    record_hip_error((int32_t)e);
+    return fail(AGG_E_HIP);
+  }
+  *out = s;
+  return AGG_OK;
+}
+
+int agg_serve_run(agg_server_t s, const agg_request* reqs, int32_t n, agg_result* results,
+                  agg_request_stats* stats, agg_serve_summary* summary) {
+  if (!s || (n > 0 && (!results || !stats)) || !summary) return AGG_E_INVALID;
+  const int vr = validate(&s->cfg, reqs, n, true, s->device);
+  if (vr != AGG_OK) return vr;
+  HipExecutor ex(s);
+  Scheduler sched(s->cfg, ex);
+  sched.cur_ids_.resize((size_t)n);
+  for (int32_t i = 0; i < n; ++i) sched.cur_ids_[(size_t)i] = reqs[i].column_id;
+  const int rc = sched.run(reqs, n, results, stats, summary);
+  for (int i = 0; i < s->slots; ++i) (void)hipStreamSynchronize(s->comp[i]);
+  return rc;
+}
+
+int agg_serve_destroy(agg_server_t s) {
+  if (!s) return AGG_E_INVALID;
+  (void)hipDeviceSynchronize();
+  server_release(s);
+  return AGG_OK;
+}
+
+int agg_serve_simulate(const agg_serve_config* cfg, const agg_request* reqs, int32_t n, double pcie_gbs,
+                       double hbm_gbs, double launch_s, agg_request_stats* stats, agg_serve_summary* summary) {
+  if (!summary || (n > 0 && !stats) || !(pcie_gbs > 0) || !(hbm_gbs > 0) || !(launch_s >= 0))
+    return AGG_E_INVALID;
+  const int vr = validate(cfg, reqs, n, false, 0);
+  if (vr != AGG_OK) return vr;
+  std::vector<agg_result> results((size_t)std::max(n, 1));
+  SimExecutor ex(cfg->max_slots, pcie_gbs, hbm_gbs, launch_s);
+  Scheduler sched(*cfg, ex);
+  sched.cur_ids_.resize((size_t)n);
+  for (int32_t i = 0; i < n; ++i) sched.cur_ids_[(size_t)i] = reqs[i].column_id;
+  return sched.run(reqs, n, results.data(), stats, summary);
+}
+
+}  // extern "C"
