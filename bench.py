@@ -190,7 +190,7 @@ def bench_serve(agg, torch, host_i32, dev_i32, full=False):
     budget = 200 * 10**9
     free, _ = torch.cuda.mem_get_info()
     budget = min(budget, int(free - (8 << 30)))
-    srv = agg.Server(hbm_budget_bytes=budget, max_slots=8, cache_shipped=False)
+    srv = agg.Server(hbm_budget_bytes=budget, max_slots=8, cache_shipped=False, max_shipping=2)
     t0 = time.time()
     results, stats, sm = srv.run(reqs)
     wall = time.time() - t0
@@ -199,7 +199,7 @@ def bench_serve(agg, torch, host_i32, dev_i32, full=False):
     lat_res = [s["done_s"] - s["arrival_s"] for s, q in zip(stats, reqs) if q["resident"]]
     lat_ship = [s["done_s"] - s["arrival_s"] for s, q in zip(stats, reqs) if not q["resident"]]
     return {"requests": nreq, "n_range": [10_000, n_max], "arrival_rate_per_s": round(rate, 1),
-            "hbm_budget_bytes": budget, "max_slots": 8,
+            "hbm_budget_bytes": budget, "max_slots": 8, "max_shipping": 2,
             "completed": sm["completed"], "failed": sm["failed"],
             "p50_ms": round(agg.percentile(lat, 50) * 1e3, 3), "p99_ms": round(agg.percentile(lat, 99) * 1e3, 3),
             "resident_p50_ms": round(agg.percentile(lat_res, 50) * 1e3, 3),

@@ -240,6 +240,10 @@ typedef struct agg_serve_config {
                                   (LRU eviction by need), serving later requests with the
                                   same column_id without PCIe traffic */
     int64_t chunk_bytes;       /* copy / scan pipelining chunk for shipped columns */
+    int32_t max_shipping;      /* shipped requests in flight at once, 1..max_slots: they
+                                  share one PCIe link, so more only stretches each of them
+                                  and holds slots that resident requests could use */
+    int32_t reserved;
 } agg_serve_config;
 
 typedef struct agg_request_stats {
@@ -268,10 +272,10 @@ int agg_serve_create(agg_server_t* out, const agg_serve_config* cfg);
 
 /* Serve reqs[0..n) in real time on the current device.  The scheduler
  * releases each request at its arrival time, admits waiting requests in
- * arrival order whenever a slot is free and, for a shipped request, the
- * arena has room (evicting idle cached columns in LRU order); a shipped
- * request that does not fit holds back later shipped requests but not
- * resident or cached ones.  Each admitted request runs the agg_run kernels
+ * arrival order whenever a slot is free and, for a shipped request, fewer
+ * than max_shipping shipped requests are in flight and the arena has room
+ * (evicting idle cached columns in LRU order); a shipped request that cannot
+ * start holds back later shipped requests but not resident or cached ones.  Each admitted request runs the agg_run kernels
  * (same canonical shape, hence the same bits as alone) on its slot's
  * streams, copies of shipped chunks overlapping the scan of earlier chunks.
  * Fills results[i] (host memory) and stats[i]; returns when all are done.

@@ -76,7 +76,8 @@ class Request(ctypes.Structure):
 
 class ServeConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
-                ("cache_shipped", ctypes.c_int32), ("chunk_bytes", ctypes.c_int64)]
+                ("cache_shipped", ctypes.c_int32), ("chunk_bytes", ctypes.c_int64),
+                ("max_shipping", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class RequestStats(ctypes.Structure):
@@ -429,16 +430,17 @@ def _requests(reqs) -> "ctypes.Array":
     return arr
 
 
-def _config(hbm_budget_bytes, max_slots, cache_shipped, chunk_bytes) -> ServeConfig:
-    return ServeConfig(int(hbm_budget_bytes), int(max_slots), 1 if cache_shipped else 0, int(chunk_bytes))
+def _config(hbm_budget_bytes, max_slots, cache_shipped, chunk_bytes, max_shipping) -> ServeConfig:
+    ms = min(int(max_slots), 2) if max_shipping is None else int(max_shipping)
+    return ServeConfig(int(hbm_budget_bytes), int(max_slots), 1 if cache_shipped else 0, int(chunk_bytes), ms, 0)
 
 
 class Server:
     """agg_serve_create / agg_serve_run: continuous admission of requests on the GPU."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, cache_shipped: bool = True,
-                 chunk_bytes: int = 64 << 20):
-        self.cfg = _config(hbm_budget_bytes, max_slots, cache_shipped, chunk_bytes)
+                 chunk_bytes: int = 64 << 20, max_shipping: Optional[int] = None):
+        self.cfg = _config(hbm_budget_bytes, max_slots, cache_shipped, chunk_bytes, max_shipping)
         h = ctypes.c_void_p()
         _check(lib().agg_serve_create(ctypes.byref(h), ctypes.byref(self.cfg)), "agg_serve_create")
         self._h = h
@@ -469,9 +471,9 @@ class Server:
 
 def serve_simulate(reqs: list, hbm_budget_bytes: int, max_slots: int = 8, cache_shipped: bool = True,
                    chunk_bytes: int = 64 << 20, pcie_gbs: float = 55.0, hbm_gbs: float = 7000.0,
-                   launch_s: float = 10e-6):
+                   launch_s: float = 10e-6, max_shipping: Optional[int] = None):
     """The serving scheduler on the CPU with a simulated clock (no device)."""
-    cfg = _config(hbm_budget_bytes, max_slots, cache_shipped, chunk_bytes)
+    cfg = _config(hbm_budget_bytes, max_slots, cache_shipped, chunk_bytes, max_shipping)
     arr = _requests(reqs)
     n = len(reqs)
     st = (RequestStats * max(1, n))()

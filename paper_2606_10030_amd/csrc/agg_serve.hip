@@ -154,7 +154,7 @@ class Scheduler {
     std::vector<Job> slot(cfg_.max_slots);
     std::vector<bool> busy(cfg_.max_slots, false);
     std::deque<int> pending;
-    int next = 0, finished = 0, nbusy = 0, peak_busy = 0, hits = 0, failed = 0;
+    int next = 0, finished = 0, nbusy = 0, peak_busy = 0, hits = 0, failed = 0, nship = 0;
     int64_t scanned = 0, shipped = 0;
     double first = n ? reqs[0].arrival_s : 0.0, last = 0.0;
     for (int i = 0; i < n; ++i) {
@@ -186,6 +186,7 @@ class Scheduler {
         release(j);
         busy[s] = false;
         --nbusy;
+        nship -= j.ship ? 1 : 0;
         ++finished;
         progress = true;
       }
@@ -216,7 +217,8 @@ class Scheduler {
           it = pending.erase(it);
           progress = true;
           continue;
-        } else if (!memory_blocked && (j.bytes == 0 || cache_.make_room(arena_, j.bytes, &j.off))) {
+        } else if (!memory_blocked && (j.bytes == 0 || (nship < cfg_.max_shipping &&
+                                                         cache_.make_room(arena_, j.bytes, &j.off)))) {
           j.ship = j.bytes > 0;
           j.from_arena = j.bytes > 0;
           admit = true;
@@ -245,6 +247,7 @@ class Scheduler {
           slot[s] = j;
           busy[s] = true;
           ++nbusy;
+          nship += j.ship ? 1 : 0;
           peak_busy = std::max(peak_busy, nbusy);
           scanned += j.bytes;
           shipped += rs.bytes_shipped;
@@ -289,6 +292,27 @@ class Scheduler {
 };
 
 // ------------------------------------------------------------ GPU executor
+// Chunks of a shipped column in flight per slot.  The host drives the
+// pipeline: it starts the scan of a chunk only after seeing its copy finish,
+// and then starts the next copy, so no compute queue ever holds a wait on a
+// PCIe copy (with more streams than hardware queues, such a wait would also
+// stall unrelated requests queued behind it).
+constexpr int kPipe = 4;
+
+struct SlotRun {
+  bool ship = false;
+  bool combined = false;
+  ScanArgs a{};
+  CombineArgs c{};
+  const void* scan_fn = nullptr;
+  const void* comb_fn = nullptr;
+  agg_tune t{};
+  int64_t nseg = 0, seg_bytes = 0, cs = 1, nchunks = 0, bytes = 0;
+  int64_t next_copy = 0, next_scan = 0;
+  const char* host = nullptr;
+  char* dst = nullptr;
+};
+
 class HipExecutor : public Executor {
  public:
   explicit HipExecutor(agg_server_s* s);
@@ -305,8 +329,13 @@ class HipExecutor : public Executor {
   }
 
  private:
+  int copy_chunk(int slot, int64_t k);
+  int scan_chunk(int slot, int64_t k);
+  int finish_launches(int slot);
+  int fail(int slot, int rc);
   agg_server_s* s_;
   agg_result* res_host_;
+  std::vector<SlotRun> run_;
   std::chrono::steady_clock::time_point t0_;
 };
 
@@ -353,6 +382,7 @@ class SimExecutor : public Executor {
 int validate(const agg_serve_config* cfg, const agg_request* reqs, int32_t n, bool need_device, int dev) {
   if (!cfg || n < 0 || (n > 0 && !reqs)) return AGG_E_INVALID;
   if (cfg->max_slots < 1 || cfg->max_slots > kMaxSlots || cfg->hbm_budget_bytes < 0) return AGG_E_INVALID;
+  if (cfg->max_shipping < 1 || cfg->max_shipping > cfg->max_slots) return AGG_E_INVALID;
   if (cfg->chunk_bytes < (1 << 20) || cfg->chunk_bytes > ((int64_t)1 << 32)) return AGG_E_INVALID;
   for (int32_t i = 0; i < n; ++i) {
     const agg_request& r = reqs[i];
@@ -382,7 +412,7 @@ struct agg_server_s {
   int slots = 0;
   hipStream_t comp[kMaxSlots] = {};
   hipStream_t copy[kMaxSlots] = {};
-  hipEvent_t copied[kMaxSlots] = {};
+  hipEvent_t copied[kMaxSlots][kPipe] = {};
   hipEvent_t done[kMaxSlots] = {};
   uint64_t* part = nullptr;       // slots x kSegTarget partial slots
   agg_result* res_host = nullptr;  // slots results, page-locked host memory
@@ -395,7 +425,8 @@ void server_release(agg_server_s* s) {
   for (int i = 0; i < s->slots; ++i) {
     if (s->comp[i]) (void)hipStreamDestroy(s->comp[i]);
     if (s->copy[i]) (void)hipStreamDestroy(s->copy[i]);
-    if (s->copied[i]) (void)hipEventDestroy(s->copied[i]);
+    for (int k = 0; k < kPipe; ++k)
+      if (s->copied[i][k]) (void)hipEventDestroy(s->copied[i][k]);
     if (s->done[i]) (void)hipEventDestroy(s->done[i]);
   }
   if (s->part) (void)hipFree(s->part);
@@ -407,64 +438,23 @@ void server_release(agg_server_s* s) {
 }  // namespace
 
 agg::serve::HipExecutor::HipExecutor(agg_server_s* s)
-    : s_(s), res_host_(s->res_host), t0_(std::chrono::steady_clock::now()) {}
+    : s_(s), res_host_(s->res_host), run_((size_t)s->slots), t0_(std::chrono::steady_clock::now()) {}
 
-int agg::serve::HipExecutor::start(int slot, const agg_request& r, const Job& j) {
-  hipStream_t comp = s_->comp[slot];
-  agg_shape sh;
-  shape_of(r.dtype, r.n, &sh);
-  agg_tune t;
-  tune_for(j.kind, AGG_SRC_DEVICE, j.bytes, &t);
-  const char* col = j.from_arena ? s_->arena + j.off : static_cast<const char*>(r.ptr);
-  const bool aligned = (reinterpret_cast<uintptr_t>(col) & 15) == 0;
-  uint64_t* part = s_->part + (size_t)slot * kSegTarget;
-  ScanArgs a;
-  a.col_bytes = j.bytes;
-  a.seg_bytes = sh.seg_bytes;
-  a.part = part;
-  a.base = col;
-  a.base_seg = 0;
-  CombineArgs c;
-  c.part = part;
-  c.nseg = sh.nseg;
-  c.out = res_host_ + slot;
-  c.n = r.n;
-  c.is_avg = r.op == AGG_AVG;
-  c.prec_used = (r.dtype == AGG_F32 && (r.op == AGG_SUM || r.op == AGG_AVG)) ? r.prec : -1;
-  const void* scan_fn = scan_kernel_ptr(j.kind, t.unroll, t.nontemporal != 0, aligned);
-  const void* comb_fn = combine_kernel_ptr(j.kind);
-  if (!scan_fn || !comb_fn) return AGG_E_INVALID;
-  const int cu = device_cu(s_->device);
-  if (sh.nseg > 0 && j.ship) {
-    // copy chunks of whole segments on the copy stream; scan each as it lands
-    const int64_t cs = std::max<int64_t>(1, s_->cfg.chunk_bytes / sh.seg_bytes);
-    const char* host = static_cast<const char*>(r.ptr);
-    char* dst = s_->arena + j.off;
-    for (int64_t lo = 0; lo < sh.nseg; lo += cs) {
-      const int64_t hi = std::min(sh.nseg, lo + cs);
-      const int64_t b0 = lo * sh.seg_bytes;
-      const int64_t nb = std::min(j.bytes, hi * sh.seg_bytes) - b0;
-      hipError_t e = hipMemcpyAsync(dst + b0, host + b0, (size_t)nb, hipMemcpyHostToDevice, s_->copy[slot]);
-      if (e == hipSuccess) e = hipEventRecord(s_->copied[slot], s_->copy[slot]);
-      if (e == hipSuccess) e = hipStreamWaitEvent(comp, s_->copied[slot], 0);
-      if (e != hipSuccess) {
-        record_hip_error((int32_t)e);
-        return AGG_E_HIP;
-      }
-      a.seg_lo = lo;
-      a.seg_hi = hi;
-      const int rc = launch(scan_fn, grid_for(t, cu, hi - lo), 64 * t.waves_per_block, &a, comp);
-      if (rc != AGG_OK) return rc;
-    }
-  } else if (sh.nseg > 0) {
-    a.seg_lo = 0;
-    a.seg_hi = sh.nseg;
-    const int rc = launch(scan_fn, grid_for(t, cu, sh.nseg), 64 * t.waves_per_block, &a, comp);
-    if (rc != AGG_OK) return rc;
-  }
-  int rc = launch(comb_fn, 1, kCombineThreads, &c, comp);
-  if (rc != AGG_OK) return rc;
-  const hipError_t e = hipEventRecord(s_->done[slot], comp);
+int agg::serve::HipExecutor::fail(int slot, int rc) {
+  // let anything already queued for this slot drain before its memory is reused
+  (void)hipStreamSynchronize(s_->copy[slot]);
+  (void)hipStreamSynchronize(s_->comp[slot]);
+  (void)hipGetLastError();
+  return rc;
+}
+
+int agg::serve::HipExecutor::copy_chunk(int slot, int64_t k) {
+  SlotRun& r = run_[slot];
+  const int64_t lo = k * r.cs, hi = std::min(r.nseg, lo + r.cs);
+  const int64_t b0 = lo * r.seg_bytes;
+  const int64_t nb = std::min(r.bytes, hi * r.seg_bytes) - b0;
+  hipError_t e = hipMemcpyAsync(r.dst + b0, r.host + b0, (size_t)nb, hipMemcpyHostToDevice, s_->copy[slot]);
+  if (e == hipSuccess) e = hipEventRecord(s_->copied[slot][k % kPipe], s_->copy[slot]);
   if (e != hipSuccess) {
     record_hip_error((int32_t)e);
     return AGG_E_HIP;
@@ -472,12 +462,97 @@ int agg::serve::HipExecutor::start(int slot, const agg_request& r, const Job& j)
   return AGG_OK;
 }
 
+int agg::serve::HipExecutor::scan_chunk(int slot, int64_t k) {
+  SlotRun& r = run_[slot];
+  r.a.seg_lo = k * r.cs;
+  r.a.seg_hi = std::min(r.nseg, r.a.seg_lo + r.cs);
+  return launch(r.scan_fn, grid_for(r.t, device_cu(s_->device), r.a.seg_hi - r.a.seg_lo),
+                64 * r.t.waves_per_block, &r.a, s_->comp[slot]);
+}
+
+int agg::serve::HipExecutor::finish_launches(int slot) {
+  SlotRun& r = run_[slot];
+  const int rc = launch(r.comb_fn, 1, kCombineThreads, &r.c, s_->comp[slot]);
+  if (rc != AGG_OK) return rc;
+  const hipError_t e = hipEventRecord(s_->done[slot], s_->comp[slot]);
+  if (e != hipSuccess) {
+    record_hip_error((int32_t)e);
+    return AGG_E_HIP;
+  }
+  r.combined = true;
+  return AGG_OK;
+}
+
+int agg::serve::HipExecutor::start(int slot, const agg_request& req, const Job& j) {
+  SlotRun& r = run_[slot];
+  r = SlotRun();
+  agg_shape sh;
+  shape_of(req.dtype, req.n, &sh);
+  tune_for(j.kind, AGG_SRC_DEVICE, j.bytes, &r.t);
+  const char* col = j.from_arena ? s_->arena + j.off : static_cast<const char*>(req.ptr);
+  const bool aligned = (reinterpret_cast<uintptr_t>(col) & 15) == 0;
+  uint64_t* part = s_->part + (size_t)slot * kSegTarget;
+  r.a.col_bytes = j.bytes;
+  r.a.seg_bytes = sh.seg_bytes;
+  r.a.part = part;
+  r.a.base = col;
+  r.a.base_seg = 0;
+  r.c.part = part;
+  r.c.nseg = sh.nseg;
+  r.c.out = res_host_ + slot;
+  r.c.n = req.n;
+  r.c.is_avg = req.op == AGG_AVG;
+  r.c.prec_used = (req.dtype == AGG_F32 && (req.op == AGG_SUM || req.op == AGG_AVG)) ? req.prec : -1;
+  r.scan_fn = scan_kernel_ptr(j.kind, r.t.unroll, r.t.nontemporal != 0, aligned);
+  r.comb_fn = combine_kernel_ptr(j.kind);
+  if (!r.scan_fn || !r.comb_fn) return AGG_E_INVALID;
+  r.nseg = sh.nseg;
+  r.seg_bytes = sh.seg_bytes;
+  r.bytes = j.bytes;
+  if (sh.nseg > 0 && j.ship) {
+    r.ship = true;
+    r.cs = std::max<int64_t>(1, s_->cfg.chunk_bytes / sh.seg_bytes);
+    r.nchunks = ceil_div(sh.nseg, r.cs);
+    r.host = static_cast<const char*>(req.ptr);
+    r.dst = s_->arena + j.off;
+    for (; r.next_copy < std::min<int64_t>(kPipe, r.nchunks); ++r.next_copy) {
+      const int rc = copy_chunk(slot, r.next_copy);
+      if (rc != AGG_OK) return fail(slot, rc);
+    }
+    return AGG_OK;
+  }
+  if (sh.nseg > 0) {
+    r.cs = sh.nseg;
+    const int rc = scan_chunk(slot, 0);
+    if (rc != AGG_OK) return fail(slot, rc);
+  }
+  const int rc = finish_launches(slot);
+  return rc == AGG_OK ? rc : fail(slot, rc);
+}
+
 int agg::serve::HipExecutor::poll(int slot) {
+  SlotRun& r = run_[slot];
+  if (r.ship && !r.combined) {
+    while (r.next_scan < r.next_copy) {
+      const hipError_t e = hipEventQuery(s_->copied[slot][r.next_scan % kPipe]);
+      if (e == hipErrorNotReady) break;
+      if (e != hipSuccess) {
+        record_hip_error((int32_t)e);
+        return fail(slot, AGG_E_HIP);
+      }
+      int rc = scan_chunk(slot, r.next_scan++);
+      if (rc == AGG_OK && r.next_copy < r.nchunks) rc = copy_chunk(slot, r.next_copy++);
+      if (rc != AGG_OK) return fail(slot, rc);
+    }
+    if (r.next_scan < r.nchunks) return 0;
+    const int rc = finish_launches(slot);
+    if (rc != AGG_OK) return fail(slot, rc);
+  }
   const hipError_t e = hipEventQuery(s_->done[slot]);
   if (e == hipSuccess) return 1;
   if (e == hipErrorNotReady) return 0;
   record_hip_error((int32_t)e);
-  return AGG_E_HIP;
+  return fail(slot, AGG_E_HIP);
 }
 
 extern "C" {
@@ -522,7 +597,10 @@ int agg_serve_create(agg_server_t* out, const agg_serve_config* cfg) {
     s->slots = i + 1;
     if ((e = hipStreamCreateWithFlags(&s->comp[i], hipStreamNonBlocking)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&s->copy[i], hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&s->copied[i], hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s->copied[i][0], hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s->copied[i][1], hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s->copied[i][2], hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s->copied[i][3], hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&s->done[i], hipEventDisableTiming)) != hipSuccess) {
       record_hip_error((int32_t)e);
       return fail(AGG_E_HIP);

@@ -105,3 +105,24 @@ def test_invalid_requests_are_rejected():
 def test_percentile_nearest_rank():
     xs = list(range(1, 101))
     assert agg.percentile(xs, 50) == 50 and agg.percentile(xs, 99) == 99 and agg.percentile(xs, 100) == 100
+
+
+def test_shipping_cap_keeps_resident_latency_low():
+    specs = request_stream(600, seed=3, n_min=10_000, n_max=1 << 30, rate_per_s=150.0,
+                           resident_frac=0.3, hot_items=1 << 30, arena_items=1 << 30)
+    reqs = reqs_of(specs)
+    out = {}
+    for cap in (8, 2):
+        st, sm = agg.serve_simulate(reqs, hbm_budget_bytes=200 * 10**9, max_slots=8, cache_shipped=False,
+                                    max_shipping=cap)
+        res = [s["done_s"] - s["arrival_s"] for s, q in zip(st, specs) if q["resident"]]
+        out[cap] = agg.percentile(res, 99)
+        # never more shipped requests in flight than the cap
+        ev = sorted([(s["admit_s"], 1) for s, q in zip(st, specs) if not q["resident"]] +
+                    [(s["done_s"], -1) for s, q in zip(st, specs) if not q["resident"]], key=lambda e: (e[0], e[1]))
+        live = peak = 0
+        for _, d in ev:
+            live += d
+            peak = max(peak, live)
+        assert peak <= cap
+    assert out[2] < out[8]
