@@ -314,7 +314,8 @@ def main():
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom, dom_bytes),
-                "kernel": f"scan {dom} (agg_run: one launch per call)",
+                "kernel": f"scan {dom}: HIP events bracket each agg_run call (scan launch + one-workgroup "
+                          "combine launch), on the stream both are launched on",
                 "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_ms, 4),
                 "launches_timed": len(dom_cells) * args.steps}
 
