@@ -215,6 +215,54 @@ int agg_tune_save(const char* path);
 int agg_tune_load(const char* path);
 int agg_tune_clear(void);
 
+/* ---- compressed int32 columns (frame of reference + bit packing) ---- */
+
+/* The paper finds host-to-device transfer to dominate end-to-end time and
+ * names compression as the way to cut it (Sections 5.3 and 8).  A packed
+ * column stores int32 items in blocks of AGG_PACK_BLOCK items: block b holds
+ * items [b*2048, b*2048 + 2048) as base = their minimum and, for each item,
+ * d = item - base (< 2^32) in `bits` bits, bits = bit width of (max - base).
+ * Payload of a block: 64 * bits 32-bit words at payload[word_off ...]; word
+ * j * 64 + l is word j of lane l, and lane l's `bits` words hold the d of
+ * items b*2048 + 32*l + i, i = 0..31, item i in bits [i*bits, (i+1)*bits) of
+ * the lane's words taken as one little-endian bit string.  Items past n in
+ * the last block are encoded as d = 0.  Every item is recovered exactly, so
+ * SUM / MIN / MAX / COUNT / AVG of a packed column equal those of the raw
+ * column bit for bit. */
+#define AGG_PACK_BLOCK 2048
+
+typedef struct agg_packed_block {  /* 16 bytes */
+    int32_t base;
+    uint32_t bits;      /* 0..32 */
+    int64_t word_off;   /* first payload word of the block */
+} agg_packed_block;
+
+typedef struct agg_packed {
+    const agg_packed_block* blocks;  /* nblocks = ceil(n / 2048) entries */
+    const uint32_t* payload;
+    int64_t n;                       /* items */
+    int64_t payload_words;
+    int32_t dtype;                   /* AGG_I32 */
+    int32_t reserved;
+} agg_packed;
+
+/* Upper bound of payload words for n items (every block at 32 bits). */
+int agg_pack_bound(int64_t n, int64_t* max_payload_words);
+
+/* Encode x[0..n) (host memory) into blocks[ceil(n/2048)] and payload
+ * (host memory of payload_cap words) with `threads` host threads (<= 0: one
+ * per core, at most 64); *payload_words receives the words used.  Pure host
+ * code, no device needed. */
+int agg_pack_i32(const int32_t* x, int64_t n, agg_packed_block* blocks, uint32_t* payload,
+                 int64_t payload_cap, int64_t* payload_words, int32_t threads);
+
+/* Aggregate a packed column with a plan for dtype AGG_I32 (any op) whose
+ * src is AGG_SRC_DEVICE (blocks and payload in device memory) or
+ * AGG_SRC_ZEROCOPY (in page-locked host memory, read by the kernel over PCIe
+ * as it decodes).  n <= the plan's max_n.  Enqueues the decoding scan and the
+ * combine on `stream`; results equal agg_run on the raw column. */
+int agg_run_packed(agg_plan_t plan, const agg_packed* col, agg_result* out, void* stream);
+
 /* ---- serving: continuous admission of requests (agg_serve) ---- */
 
 typedef struct agg_server_s* agg_server_t;

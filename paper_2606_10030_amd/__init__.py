@@ -97,6 +97,12 @@ def _struct_dict(x) -> dict:
     return {f: getattr(x, f) for f, _ in x._fields_ if f != "reserved"}
 
 
+class Packed(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_void_p), ("payload", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("payload_words", ctypes.c_int64), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+PACK_BLOCK = 2048
 RESULT_BYTES = ctypes.sizeof(Result)
 assert RESULT_BYTES == 32
 
@@ -147,6 +153,9 @@ def lib():
         "agg_serve_simulate": ([ctypes.POINTER(ServeConfig), ctypes.POINTER(Request), i32, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, ctypes.POINTER(RequestStats),
                                 ctypes.POINTER(ServeSummary)], ctypes.c_int),
+        "agg_pack_bound": ([i64, ctypes.POINTER(i64)], ctypes.c_int),
+        "agg_pack_i32": ([vp, i64, vp, vp, i64, ctypes.POINTER(i64), i32], ctypes.c_int),
+        "agg_run_packed": ([vp, ctypes.POINTER(Packed), vp, vp], ctypes.c_int),
         "agg_strerror": ([i32], ctypes.c_char_p),
         "agg_last_hip_error": ([], i32),
     }
@@ -333,6 +342,22 @@ class Plan:
             s.synchronize()
         return parse_results(self._host_out.numpy().tobytes(), [(self.dtype, self.op)])[0]
 
+    def enqueue_packed(self, packed: "PackedColumn", out, stream=None) -> None:
+        """Enqueue agg_run_packed on a PackedColumn in device (src=device) or
+        pinned host memory (src=zerocopy)."""
+        st = packed.struct()
+        optr = out if isinstance(out, int) else out.data_ptr()
+        _check(lib().agg_run_packed(self._h, ctypes.byref(st), optr, _stream_handle(stream)), "agg_run_packed")
+
+    def run_packed(self, packed: "PackedColumn", stream=None) -> dict:
+        torch = _torch()
+        if self._host_out is None:
+            self._host_out = torch.zeros(RESULT_BYTES, dtype=torch.uint8, pin_memory=True)
+        s = torch.cuda.current_stream() if stream is None else stream
+        self.enqueue_packed(packed, self._host_out, stream=s)
+        s.synchronize()
+        return parse_results(self._host_out.numpy().tobytes(), [(self.dtype, self.op)])[0]
+
     def close(self):
         if getattr(self, "_h", None):
             lib().agg_plan_destroy(self._h)
@@ -490,3 +515,70 @@ def percentile(xs, q: float) -> float:
         return float("nan")
     k = max(0, min(len(v) - 1, int(-(-q * len(v) // 100)) - 1))
     return v[k]
+
+
+# ------------------------------------------------------------------ packed columns
+def _np():
+    import numpy as np
+    return np
+
+
+BLOCK_DTYPE = None
+
+
+def block_dtype():
+    global BLOCK_DTYPE
+    if BLOCK_DTYPE is None:
+        np = _np()
+        BLOCK_DTYPE = np.dtype([("base", "<i4"), ("bits", "<u4"), ("word_off", "<i8")])
+    return BLOCK_DTYPE
+
+
+@dataclass
+class PackedColumn:
+    """A frame-of-reference + bit-packed int32 column (layout: agg_packed in agg.h).
+    `blocks` and `payload` are numpy arrays (host) or torch tensors (device or pinned)."""
+    blocks: object
+    payload: object
+    n: int
+    payload_words: int
+
+    def _ptr(self, x) -> int:
+        if x is None:
+            return 0
+        return x.data_ptr() if hasattr(x, "data_ptr") else x.ctypes.data
+
+    def struct(self) -> Packed:
+        return Packed(self._ptr(self.blocks), self._ptr(self.payload), self.n, self.payload_words, I32, 0)
+
+    @property
+    def nbytes(self) -> int:
+        return 16 * (-(-self.n // PACK_BLOCK)) + 4 * self.payload_words
+
+    def to(self, where: str) -> "PackedColumn":
+        """Copy to 'cuda' (device) or 'pinned' (page-locked host) torch tensors."""
+        torch = _torch()
+        np = _np()
+        b = torch.from_numpy(np.ascontiguousarray(self.blocks).view(np.uint8).copy())
+        p = torch.from_numpy(np.ascontiguousarray(self.payload).view(np.int32).copy())
+        if where == "pinned":
+            return PackedColumn(b.pin_memory(), p.pin_memory(), self.n, self.payload_words)
+        return PackedColumn(b.to(where), p.to(where), self.n, self.payload_words)
+
+
+def pack_i32(x, threads: int = 0) -> PackedColumn:
+    """Encode an int32 column (numpy array or CPU tensor) on the host."""
+    np = _np()
+    if hasattr(x, "numpy"):
+        x = x.numpy()
+    x = np.ascontiguousarray(x, dtype=np.int32)
+    n = x.size
+    bound = ctypes.c_int64()
+    _check(lib().agg_pack_bound(n, ctypes.byref(bound)), "agg_pack_bound")
+    blocks = np.zeros(-(-n // PACK_BLOCK), dtype=block_dtype())
+    payload = np.zeros(max(1, bound.value), dtype=np.uint32)
+    used = ctypes.c_int64()
+    _check(lib().agg_pack_i32(x.ctypes.data if n else None, n, blocks.ctypes.data if n else None,
+                              payload.ctypes.data, payload.size, ctypes.byref(used), int(threads)),
+           "agg_pack_i32")
+    return PackedColumn(blocks, payload[:max(1, used.value)].copy(), n, used.value)

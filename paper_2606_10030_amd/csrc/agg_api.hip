@@ -496,6 +496,74 @@ int agg_run(agg_plan_t p, const void* col, int64_t n, agg_result* out, void* str
   return launch(combine_fn, 1, kCombineThreads, &c, stream);
 }
 
+int agg_run_packed(agg_plan_t p, const agg_packed* col, agg_result* out, void* stream_v) {
+  if (!p || !col || !out || p->dtype != AGG_I32 || col->dtype != AGG_I32) return AGG_E_INVALID;
+  if (p->src != AGG_SRC_DEVICE && p->src != AGG_SRC_ZEROCOPY) return AGG_E_INVALID;
+  const int64_t n = col->n;
+  if (n < 0 || n > p->max_n || col->payload_words < 0) return AGG_E_INVALID;
+  const int64_t nblocks = ceil_div(n, AGG_PACK_BLOCK);
+  if (nblocks > 0 && !col->blocks) return AGG_E_INVALID;
+  if (col->payload_words > 0 && !col->payload) return AGG_E_INVALID;
+  if (col->payload_words > nblocks * 64 * 32) return AGG_E_INVALID;
+  const int32_t kind_src = p->src == AGG_SRC_ZEROCOPY ? AGG_SRC_PINNED_HOST : AGG_SRC_DEVICE;
+  if (nblocks > 0)
+    RET_IF(check_pointer(col->blocks, nblocks * (int64_t)sizeof(agg_packed_block), kind_src, p->device));
+  if (col->payload_words > 0) RET_IF(check_pointer(col->payload, col->payload_words * 4, kind_src, p->device));
+  RET_IF(check_out_pointer(out, sizeof(agg_result), p->device));
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  CombineArgs c;
+  c.part = p->part;
+  c.out = out;
+  c.n = n;
+  c.is_avg = p->op == AGG_AVG;
+  c.prec_used = -1;
+  c.nseg = 0;
+  if (p->op == AGG_COUNT) {  // n, no decoding needed
+    const void* comb = combine_kernel_ptr(p->kind);
+    agg_shape s;
+    shape_of(p->dtype, n, &s);
+    if (s.nseg > 0) {  // count through the plain coverage kernel (issues no loads)
+      ScanArgs a;
+      a.base = nullptr;
+      a.col_bytes = n * 4;
+      a.seg_bytes = s.seg_bytes;
+      a.seg_lo = 0;
+      a.seg_hi = s.nseg;
+      a.base_seg = 0;
+      a.part = p->part;
+      const void* fn = scan_kernel_ptr(p->kind, p->tune.unroll, p->tune.nontemporal != 0, true);
+      RET_IF(launch(fn, grid_for(p->tune, g_dev[p->device].cu, s.nseg), 64 * p->tune.waves_per_block, &a, stream));
+    }
+    c.nseg = s.nseg;
+    return launch(comb, 1, kCombineThreads, &c, stream);
+  }
+  const void* fn = packed_scan_kernel_ptr(p->kind);
+  const void* comb = combine_kernel_ptr(p->kind);
+  if (!fn || !comb) return AGG_E_INVALID;
+  // The decode costs about 6 VALU operations per item, so it wants more
+  // waves than the plain scan: 8 per CU unless the plan was given parameters.
+  agg_tune t = p->tune;
+  if (!p->tune_given) {
+    t.waves_per_block = 8;
+    t.blocks_per_cu = 1;
+  }
+  // one partial per wave: at most kSegTarget waves, at most one per block
+  int64_t waves = std::min<int64_t>((int64_t)t.blocks_per_cu * g_dev[p->device].cu * t.waves_per_block,
+                                    std::max<int64_t>(nblocks, 1));
+  waves = std::min<int64_t>(waves, kSegTarget);
+  const int grid = (int)std::max<int64_t>(1, waves / t.waves_per_block);
+  PackedArgs a;
+  a.blocks = col->blocks;
+  a.payload = col->payload;
+  a.n = n;
+  a.nblocks = nblocks;
+  a.payload_words = col->payload_words;
+  a.part = p->part;
+  c.nseg = (int64_t)grid * t.waves_per_block;
+  RET_IF(launch(fn, grid, 64 * t.waves_per_block, &a, stream));
+  return launch(comb, 1, kCombineThreads, &c, stream);
+}
+
 int agg_plan_destroy(agg_plan_t plan) {
   if (!plan) return AGG_E_INVALID;
   if (plan->copy_stream) (void)hipStreamSynchronize(plan->copy_stream);

@@ -39,6 +39,18 @@ struct CombineArgs {
   int32_t prec_used;
 };
 
+// One launch of the packed-column scan: each wave folds blocks wave,
+// wave + nwaves, ... and writes one partial (integer results are exact in
+// any order, so the partials need no canonical shape).
+struct PackedArgs {
+  const agg_packed_block* blocks;
+  const uint32_t* payload;
+  int64_t n;
+  int64_t nblocks;
+  int64_t payload_words;
+  void* part;            // one partial per wave of the launch
+};
+
 // One column of a batch, as the device sees it.
 struct BatchColDev {
   const char* ptr;
@@ -92,6 +104,7 @@ void builtin_tune_for(int kind, agg_tune* out);
 
 const void* scan_kernel_ptr(int kind, int unroll, bool nontemporal, bool aligned);
 const void* combine_kernel_ptr(int kind);
+const void* packed_scan_kernel_ptr(int kind);   // K_SUM_I32, K_MIN_I32, K_MAX_I32
 const void* batch_scan_kernel_ptr(int unroll, bool nontemporal);
 const void* batch_combine_kernel_ptr();
 

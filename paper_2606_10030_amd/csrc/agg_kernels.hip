@@ -52,6 +52,89 @@ __global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
   if (threadIdx.x == 0) *a.out = finalize<K>(total, a.n, a.is_avg != 0, a.prec_used);
 }
 
+// ------------------------------------------------------------ packed columns
+// Decoding scan of a frame-of-reference + bit-packed int32 column (layout in
+// agg.h).  The bit width is uniform per block, so it selects one of 33
+// decoders in which every shift is a compile-time constant.  A lane folds
+// its 32 items as d = item - base: SUM adds valid * base + sum(d), MIN / MAX
+// take base + min(d) / max(d).
+template <int BITS, bool FULL>
+__device__ __forceinline__ void decode_lane(const uint32_t* __restrict__ p, int lane, int valid, uint64_t& sum,
+                                            uint32_t& dmin, uint32_t& dmax) {
+  uint32_t w[BITS > 0 ? BITS : 1];
+#pragma unroll
+  for (int j = 0; j < BITS; ++j) w[j] = p[j * kWave + lane];
+  uint64_t s = 0;
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+#pragma unroll
+  for (int i = 0; i < kWave / 2; ++i) {
+    uint32_t v = 0;
+    if constexpr (BITS > 0) {
+      const int pos = i * BITS, wi = pos >> 5, sh = pos & 31;
+      v = w[wi] >> sh;
+      if (sh + BITS > 32) v |= w[wi + 1] << (32 - sh);
+      if (BITS < 32) v &= (1u << BITS) - 1u;
+    }
+    if (FULL || i < valid) {
+      s += v;
+      mn = v < mn ? v : mn;
+      mx = v > mx ? v : mx;
+    }
+  }
+  sum += s;
+  dmin = mn;
+  dmax = mx;
+}
+
+template <int BITS = 0>
+__device__ __forceinline__ void decode_dispatch(uint32_t bits, bool full, const uint32_t* p, int lane, int valid,
+                                                uint64_t& sum, uint32_t& dmin, uint32_t& dmax) {
+  if constexpr (BITS <= 32) {
+    if (bits == BITS) {
+      if (full) decode_lane<BITS, true>(p, lane, valid, sum, dmin, dmax);
+      else decode_lane<BITS, false>(p, lane, valid, sum, dmin, dmax);
+      return;
+    }
+    decode_dispatch<BITS + 1>(bits, full, p, lane, valid, sum, dmin, dmax);
+  }
+}
+
+template <int K>
+__global__ void __launch_bounds__(1024) packed_scan_kernel(PackedArgs a) {
+  using F = Fold<K>;
+  using P = typename F::part;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int W = blockDim.x / kWave;
+  const int64_t nwaves = (int64_t)gridDim.x * W;
+  const int64_t wave = (int64_t)blockIdx.x * W + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  constexpr int kPerLane = AGG_PACK_BLOCK / kWave;
+  uint64_t sum = 0;              // sum of items mod 2^64 (SUM)
+  int32_t ext = K == K_MIN_I32 ? INT32_MAX : INT32_MIN;  // running MIN / MAX
+  for (int64_t b = wave; b < a.nblocks; b += nwaves) {
+    const agg_packed_block h = a.blocks[b];
+    // a block whose payload would lie outside the buffer is skipped, never read
+    if (h.bits > 32 || h.word_off < 0 || h.word_off + (int64_t)kWave * h.bits > a.payload_words) continue;
+    const int64_t left = a.n - b * AGG_PACK_BLOCK;
+    const bool full = left >= AGG_PACK_BLOCK;
+    int valid = (int)(left - (int64_t)lane * kPerLane);
+    valid = valid < 0 ? 0 : (valid > kPerLane ? kPerLane : valid);
+    uint64_t dsum = 0;
+    uint32_t dmin = 0xFFFFFFFFu, dmax = 0u;
+    decode_dispatch(h.bits, full, a.payload + h.word_off, lane, valid, dsum, dmin, dmax);
+    if constexpr (K == K_SUM_I32) {
+      sum += dsum + (uint64_t)((int64_t)valid * (int64_t)h.base);
+    } else if (valid > 0) {
+      const int32_t lo = (int32_t)((uint32_t)h.base + dmin), hi = (int32_t)((uint32_t)h.base + dmax);
+      ext = K == K_MIN_I32 ? min(ext, lo) : max(ext, hi);
+    }
+  }
+  P partial;
+  if constexpr (K == K_SUM_I32) partial = sum;
+  else partial = (int64_t)ext;
+  partial = wave_reduce(partial, PartMerge<K>());
+  if (lane == 0) reinterpret_cast<P*>(a.part)[wave] = partial;
+}
+
 // ------------------------------------------------------------ batch
 template <int K, int U, bool NT>
 __device__ __forceinline__ void batch_item(const BatchColDev& c, const WorkItem& it, uint64_t* slots,
@@ -177,6 +260,15 @@ const void* combine_lookup(int kind, std::integer_sequence<int, Ks...>) {
 const void* combine_kernel_ptr(int kind) {
   if (kind < 0 || kind >= K_NUM) return nullptr;
   return combine_lookup(kind, std::make_integer_sequence<int, K_NUM>());
+}
+
+const void* packed_scan_kernel_ptr(int kind) {
+  switch (kind) {
+    case K_SUM_I32: return reinterpret_cast<const void*>(&packed_scan_kernel<K_SUM_I32>);
+    case K_MIN_I32: return reinterpret_cast<const void*>(&packed_scan_kernel<K_MIN_I32>);
+    case K_MAX_I32: return reinterpret_cast<const void*>(&packed_scan_kernel<K_MAX_I32>);
+    default: return nullptr;
+  }
 }
 
 const void* batch_scan_kernel_ptr(int unroll, bool nontemporal) {
