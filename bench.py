@@ -338,6 +338,27 @@ def main():
         p.close()
     extra["f32_sum_modes"] = modes
 
+    # ---- fused filter + aggregate: SUM(x) WHERE y < 0 (half the items), both columns read once
+    fused = {}
+    for vdt, fdt in (("i32", "f32"), ("i64", "i32"), ("f32", "i32")):
+        p = agg.Plan(vdt, "sum", max_n=n)
+        filt = agg.make_filter(dev[fdt], None, 0, True, False)
+        o = torch.zeros(32, dtype=torch.uint8, device="cuda")
+        for _ in range(2):
+            p.enqueue_filtered(dev[vdt], filt, o, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            p.enqueue_filtered(dev[vdt], filt, o, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        b = n * (WIDTH[vdt] + WIDTH[fdt])
+        fused[f"sum_{vdt}_where_{fdt}_lt_0"] = {"ms": round(ms, 4), "GB/s": round(b / (ms * 1e-3) / 1e9, 1),
+                                                "hbm_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        p.close()
+    extra["fused_filter"] = fused
+
     # ---- latency: 2^20 int32 SUM (launch-bound)
     small = dev["i32"][: 1 << 20]
     p = agg.Plan("i32", "sum", max_n=1 << 20)

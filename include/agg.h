@@ -215,6 +215,35 @@ int agg_tune_save(const char* path);
 int agg_tune_load(const char* path);
 int agg_tune_clear(void);
 
+/* ---- fused filter + aggregate ---- */
+
+/* A range predicate on a second column of the same length: item i of the
+ * value column is aggregated when lo <= y[i] <= hi (each bound inclusive or
+ * exclusive) for the filter column y.  Integer filter columns compare as
+ * int64 against ilo / ihi, float32 ones as double against flo / fhi (NaN
+ * items are never selected; use +-infinity for an open side).  Operator
+ * fusion is the paper's stated next step (Section 8): both columns are read
+ * once in the same scan instead of materialising a selection. */
+typedef struct agg_filter {
+    const void* col;        /* filter column, device memory, aligned to its item width */
+    int32_t dtype;          /* AGG_I32 / AGG_I64 / AGG_F32 */
+    int32_t lo_inclusive;   /* 1: y >= lo; 0: y > lo */
+    int32_t hi_inclusive;   /* 1: y <= hi; 0: y < hi */
+    int32_t reserved;
+    int64_t ilo, ihi;       /* bounds for integer filter columns */
+    double flo, fhi;        /* bounds for float32 filter columns */
+} agg_filter;
+
+/* Aggregate the selected items of col[0..n) (plan src must be AGG_SRC_DEVICE).
+ * The reduction shape is the value column's canonical shape with every
+ * unselected item replaced by the function's identity, so an always-true
+ * predicate gives agg_run's bits.  COUNT = number of selected items; AVG
+ * divides by it; MIN / MAX / AVG are null when nothing is selected; the
+ * result's count field is the selected count.  (A float SUM whose selected
+ * items sum to -0.0 may come out as +0.0.) */
+int agg_run_filtered(agg_plan_t plan, const void* col, int64_t n, const agg_filter* filter,
+                     agg_result* out, void* stream);
+
 /* ---- compressed int32 columns (frame of reference + bit packing) ---- */
 
 /* The paper finds host-to-device transfer to dominate end-to-end time and

@@ -97,6 +97,31 @@ def _struct_dict(x) -> dict:
     return {f: getattr(x, f) for f, _ in x._fields_ if f != "reserved"}
 
 
+class Filter(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("lo_inclusive", ctypes.c_int32),
+                ("hi_inclusive", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ilo", ctypes.c_int64),
+                ("ihi", ctypes.c_int64), ("flo", ctypes.c_double), ("fhi", ctypes.c_double)]
+
+
+def make_filter(col, lo=None, hi=None, lo_inclusive: bool = True, hi_inclusive: bool = True,
+                dtype=None) -> Filter:
+    """A range predicate lo <=/< y <=/< hi on the filter column `col` (a device
+    tensor, or an int address with `dtype`); a missing bound is open."""
+    if isinstance(col, int):
+        ptr, dt = col, _code(dtype, DTYPES, "dtype")
+    else:
+        ptr, dt = col.data_ptr(), _dtype_of_tensor(col)
+    inf = float("inf")
+    if dt == F32:
+        flo = -inf if lo is None else float(lo)
+        fhi = inf if hi is None else float(hi)
+        return Filter(ptr, dt, int(lo_inclusive), int(hi_inclusive), 0, 0, 0, flo, fhi)
+    ilo = -(1 << 63) if lo is None else int(lo)
+    ihi = (1 << 63) - 1 if hi is None else int(hi)
+    return Filter(ptr, dt, 1 if lo is None else int(lo_inclusive), 1 if hi is None else int(hi_inclusive), 0,
+                  ilo, ihi, 0.0, 0.0)
+
+
 class Packed(ctypes.Structure):
     _fields_ = [("blocks", ctypes.c_void_p), ("payload", ctypes.c_void_p), ("n", ctypes.c_int64),
                 ("payload_words", ctypes.c_int64), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -153,6 +178,7 @@ def lib():
         "agg_serve_simulate": ([ctypes.POINTER(ServeConfig), ctypes.POINTER(Request), i32, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, ctypes.POINTER(RequestStats),
                                 ctypes.POINTER(ServeSummary)], ctypes.c_int),
+        "agg_run_filtered": ([vp, vp, i64, ctypes.POINTER(Filter), vp, vp], ctypes.c_int),
         "agg_pack_bound": ([i64, ctypes.POINTER(i64)], ctypes.c_int),
         "agg_pack_i32": ([vp, i64, vp, vp, i64, ctypes.POINTER(i64), i32], ctypes.c_int),
         "agg_run_packed": ([vp, ctypes.POINTER(Packed), vp, vp], ctypes.c_int),
@@ -340,6 +366,22 @@ class Plan:
             torch.cuda.synchronize()
         else:
             s.synchronize()
+        return parse_results(self._host_out.numpy().tobytes(), [(self.dtype, self.op)])[0]
+
+    def enqueue_filtered(self, col, filt: Filter, out, n: Optional[int] = None, stream=None) -> None:
+        """Enqueue agg_run_filtered: aggregate the items of `col` selected by `filt`."""
+        ptr, nn = self._col_args(col, n)
+        optr = out if isinstance(out, int) else out.data_ptr()
+        _check(lib().agg_run_filtered(self._h, ptr, nn, ctypes.byref(filt), optr, _stream_handle(stream)),
+               "agg_run_filtered")
+
+    def run_filtered(self, col, filt: Filter, n: Optional[int] = None, stream=None) -> dict:
+        torch = _torch()
+        if self._host_out is None:
+            self._host_out = torch.zeros(RESULT_BYTES, dtype=torch.uint8, pin_memory=True)
+        s = torch.cuda.current_stream() if stream is None else stream
+        self.enqueue_filtered(col, filt, self._host_out, n=n, stream=s)
+        s.synchronize()
         return parse_results(self._host_out.numpy().tobytes(), [(self.dtype, self.op)])[0]
 
     def enqueue_packed(self, packed: "PackedColumn", out, stream=None) -> None:

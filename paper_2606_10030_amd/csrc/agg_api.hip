@@ -287,7 +287,7 @@ int alloc_device(void** p, size_t bytes) {
   } while (0)
 
 int plan_create(agg_plan_s* p) {
-  const size_t ws_bytes = (size_t)kSegTarget * 8;
+  const size_t ws_bytes = (size_t)kSegTarget * 8 * 2;  // segment partials + selected counts
   RET_IF(alloc_device(&p->ws, ws_bytes));
   p->part = static_cast<uint64_t*>(p->ws);
   HIPCHK(hipMemset(p->ws, 0, ws_bytes));
@@ -494,6 +494,57 @@ int agg_run(agg_plan_t p, const void* col, int64_t n, agg_result* out, void* str
     p->slot_used[slot] = true;
   }
   return launch(combine_fn, 1, kCombineThreads, &c, stream);
+}
+
+int agg_run_filtered(agg_plan_t p, const void* col, int64_t n, const agg_filter* filter, agg_result* out,
+                     void* stream_v) {
+  if (!p || !filter || !out || n < 0 || n > p->max_n || (n > 0 && (!col || !filter->col))) return AGG_E_INVALID;
+  if (p->src != AGG_SRC_DEVICE) return AGG_E_INVALID;
+  const int fw = width_of(filter->dtype);
+  if (fw == 0 || (filter->lo_inclusive != 0 && filter->lo_inclusive != 1) ||
+      (filter->hi_inclusive != 0 && filter->hi_inclusive != 1))
+    return AGG_E_INVALID;
+  if (n > 0 && (reinterpret_cast<uintptr_t>(col) % (uintptr_t)p->width != 0 ||
+                reinterpret_cast<uintptr_t>(filter->col) % (uintptr_t)fw != 0))
+    return AGG_E_INVALID;
+  if (n > 0) {
+    RET_IF(check_pointer(col, n * p->width, AGG_SRC_DEVICE, p->device));
+    RET_IF(check_pointer(filter->col, n * fw, AGG_SRC_DEVICE, p->device));
+  }
+  RET_IF(check_out_pointer(out, sizeof(agg_result), p->device));
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  agg_shape s;
+  shape_of(p->dtype, n, &s);
+  const bool aligned = ((reinterpret_cast<uintptr_t>(col) | reinterpret_cast<uintptr_t>(filter->col)) & 15) == 0;
+  const void* fn = filter_scan_kernel_ptr(p->kind, filter->dtype, aligned);
+  const void* comb = filter_combine_kernel_ptr(p->kind);
+  if (!fn || !comb) return AGG_E_INVALID;
+  uint64_t* cpart = p->part + kSegTarget;
+  if (s.nseg > 0) {
+    FilterArgs a;
+    a.base = static_cast<const char*>(col);
+    a.fbase = static_cast<const char*>(filter->col);
+    a.col_bytes = n * p->width;
+    a.seg_bytes = s.seg_bytes;
+    a.nseg = s.nseg;
+    a.part = p->part;
+    a.cpart = cpart;
+    a.pred.ilo = filter->ilo;
+    a.pred.ihi = filter->ihi;
+    a.pred.flo = filter->flo;
+    a.pred.fhi = filter->fhi;
+    a.pred.lo_incl = filter->lo_inclusive;
+    a.pred.hi_incl = filter->hi_inclusive;
+    RET_IF(launch(fn, grid_for(p->tune, g_dev[p->device].cu, s.nseg), 64 * p->tune.waves_per_block, &a, stream));
+  }
+  FilterCombineArgs c;
+  c.part = p->part;
+  c.cpart = cpart;
+  c.nseg = s.nseg;
+  c.out = out;
+  c.is_avg = p->op == AGG_AVG;
+  c.prec_used = (p->dtype == AGG_F32 && (p->op == AGG_SUM || p->op == AGG_AVG)) ? p->prec : -1;
+  return launch(comb, 1, kCombineThreads, &c, stream);
 }
 
 int agg_run_packed(agg_plan_t p, const agg_packed* col, agg_result* out, void* stream_v) {

@@ -51,6 +51,34 @@ struct PackedArgs {
   void* part;            // one partial per wave of the launch
 };
 
+// The range predicate of a filtered scan, as the device sees it.
+struct RangePred {
+  int64_t ilo, ihi;
+  double flo, fhi;
+  int32_t lo_incl, hi_incl;
+};
+
+// One launch of the filtered scan: value partials and selected counts per segment.
+struct FilterArgs {
+  const char* base;      // value column
+  const char* fbase;     // filter column
+  int64_t col_bytes;
+  int64_t seg_bytes;
+  int64_t nseg;
+  void* part;            // nseg value partials
+  uint64_t* cpart;       // nseg selected counts
+  RangePred pred;
+};
+
+struct FilterCombineArgs {
+  const void* part;
+  const uint64_t* cpart;
+  int64_t nseg;
+  agg_result* out;
+  int32_t is_avg;
+  int32_t prec_used;
+};
+
 // One column of a batch, as the device sees it.
 struct BatchColDev {
   const char* ptr;
@@ -105,6 +133,8 @@ void builtin_tune_for(int kind, agg_tune* out);
 const void* scan_kernel_ptr(int kind, int unroll, bool nontemporal, bool aligned);
 const void* combine_kernel_ptr(int kind);
 const void* packed_scan_kernel_ptr(int kind);   // K_SUM_I32, K_MIN_I32, K_MAX_I32
+const void* filter_scan_kernel_ptr(int kind, int32_t filter_dtype, bool aligned);
+const void* filter_combine_kernel_ptr(int kind);
 const void* batch_scan_kernel_ptr(int unroll, bool nontemporal);
 const void* batch_combine_kernel_ptr();
 
