@@ -94,6 +94,54 @@ def counters_mode(n: int):
     log("counters mode done")
 
 
+def bench_energy(agg, torch, dev_i32, host_i32, stream):
+    """Joules per aggregation from the GPU's energy accumulator (amdsmi), for
+    the on-device SUM of a 2^30-item int32 column and the same SUM end to end
+    (zero-copy from pinned host memory); idle power measured first and also
+    subtracted ("above idle")."""
+    try:
+        import amdsmi
+        amdsmi.amdsmi_init()
+        h = amdsmi.amdsmi_get_processor_handles()[0]
+    except Exception as ex:  # telemetry not available on this host
+        return {"available": False, "reason": f"{type(ex).__name__}: {ex}"[:200]}
+
+    def joules():
+        e = amdsmi.amdsmi_get_energy_count(h)
+        return e["energy_accumulator"] * e["counter_resolution"] * 1e-6
+
+    out = {"available": True, "source": "amdsmi energy accumulator (whole GPU)"}
+    torch.cuda.synchronize()
+    j0, t0 = joules(), time.perf_counter()
+    time.sleep(1.0)
+    idle_w = (joules() - j0) / (time.perf_counter() - t0)
+    out["idle_W"] = round(idle_w, 1)
+    n = dev_i32.numel()
+    o = torch.zeros(32, dtype=torch.uint8, device="cuda")
+    for label, src, col, reps in (("on_device", "device", dev_i32, 3000), ("end_to_end_zerocopy", "zerocopy", host_i32, 25)):
+        p = agg.Plan("i32", "sum", max_n=n, src=src)
+        p.enqueue(col, o, stream=stream)
+        torch.cuda.synchronize()
+        j0, t0 = joules(), time.perf_counter()
+        for _ in range(reps):
+            p.enqueue(col, o, stream=stream)
+        torch.cuda.synchronize()
+        dt, dj = time.perf_counter() - t0, joules() - j0
+        p.close()
+        per = dj / reps
+        above = (dj - idle_w * dt) / reps
+        gb = n * 4 / 1e9
+        out[label] = {"J_per_scan": round(per, 4), "J_per_scan_above_idle": round(above, 4),
+                      "J_per_GB": round(per / gb, 4), "avg_W": round(dj / dt, 1), "scans": reps,
+                      "seconds": round(dt, 2),
+                      "J_for_1.2e9_items": round(per * 1.2e9 / n, 4)}
+    try:
+        amdsmi.amdsmi_shut_down()
+    except Exception:
+        pass
+    return out
+
+
 def bench_batch(agg, torch, stream, table):
     """4096 columns, lengths log-uniform in [1e3, 1e7], dtype uniform over int32 /
     int64 / float32, function uniform over SUM / MIN / MAX / AVG (seed 12); also
@@ -222,6 +270,7 @@ def main():
     ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-energy", action="store_true")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving with 10^4 requests of up to 2^33 int32 items (minutes of PCIe time)")
     ap.add_argument("--n", type=int, default=N_ITEMS, help=argparse.SUPPRESS)
@@ -434,6 +483,10 @@ def main():
         e2e_ms = n * 4 / (e2e["pinned_host_i32_sum"]["GB/s"] * 1e9) * 1e3
         e2e["transfer_share_of_e2e_time"] = round(1 - dev_ms / e2e_ms, 4)
         extra["e2e"] = e2e
+
+    # ---- energy per aggregation (on-device and end to end)
+    if not args.no_energy:
+        extra["energy"] = bench_energy(agg, torch, dev["i32"], host["i32"], stream)
 
     # ---- batch: 4096 mixed columns in one persistent launch under a HIP graph
     if not args.no_batch:

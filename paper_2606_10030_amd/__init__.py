@@ -115,7 +115,8 @@ def make_filter(col, lo=None, hi=None, lo_inclusive: bool = True, hi_inclusive: 
     if dt == F32:
         flo = -inf if lo is None else float(lo)
         fhi = inf if hi is None else float(hi)
-        return Filter(ptr, dt, int(lo_inclusive), int(hi_inclusive), 0, 0, 0, flo, fhi)
+        return Filter(ptr, dt, 1 if lo is None else int(lo_inclusive), 1 if hi is None else int(hi_inclusive),
+                      0, 0, 0, flo, fhi)
     ilo = -(1 << 63) if lo is None else int(lo)
     ihi = (1 << 63) - 1 if hi is None else int(hi)
     return Filter(ptr, dt, 1 if lo is None else int(lo_inclusive), 1 if hi is None else int(hi_inclusive), 0,

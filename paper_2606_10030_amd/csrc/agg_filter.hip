@@ -27,15 +27,14 @@ constexpr uint64_t item_identity() {
 template <int FT>
 __device__ __forceinline__ bool pred_test(uint32_t lo_word, uint32_t hi_word, const RangePred& q) {
   if constexpr (FT == AGG_F32) {
-    const double x = (double)__uint_as_float(lo_word);
-    const bool a = q.lo_incl ? x >= q.flo : x > q.flo;
-    const bool b = q.hi_incl ? x <= q.fhi : x < q.fhi;
-    return a && b;
+    const float x = __uint_as_float(lo_word);  // NaN fails both comparisons
+    return x >= q.flo && x <= q.fhi;
+  } else if constexpr (FT == AGG_I32) {
+    const int32_t x = (int32_t)lo_word;
+    return x >= (int32_t)q.ilo && x <= (int32_t)q.ihi;
   } else {
-    const int64_t x = FT == AGG_I32 ? (int64_t)(int32_t)lo_word : (int64_t)as_u64(lo_word, hi_word);
-    const bool a = q.lo_incl ? x >= q.ilo : x > q.ilo;
-    const bool b = q.hi_incl ? x <= q.ihi : x < q.ihi;
-    return a && b;
+    const int64_t x = (int64_t)as_u64(lo_word, hi_word);
+    return x >= q.ilo && x <= q.ihi;
   }
 }
 

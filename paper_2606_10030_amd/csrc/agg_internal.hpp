@@ -51,11 +51,13 @@ struct PackedArgs {
   void* part;            // one partial per wave of the launch
 };
 
-// The range predicate of a filtered scan, as the device sees it.
+// The range predicate of a filtered scan, as the device sees it: the host
+// turns every agg_filter into an inclusive range lo <= y <= hi in the filter
+// column's own type (int32 / int64 / float32), selecting exactly the same
+// items; an empty range has lo > hi.
 struct RangePred {
   int64_t ilo, ihi;
-  double flo, fhi;
-  int32_t lo_incl, hi_incl;
+  float flo, fhi;
 };
 
 // One launch of the filtered scan: value partials and selected counts per segment.

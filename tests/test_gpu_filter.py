@@ -121,3 +121,38 @@ def test_filter_errors(agg):
         p.run_filtered(x, agg.make_filter(hy.ctypes.data, dtype="i32"))
     with pytest.raises(agg.AggError):   # host-source plans do not filter
         agg.Plan("i32", "sum", max_n=1000, src="pinned_host").run_filtered(x.cpu().pin_memory(), agg.make_filter(y))
+
+
+def test_float_bounds_normalised_exactly(agg):
+    import torch
+    r = np.random.default_rng(12)
+    y = np.concatenate([r.standard_normal(200_000).astype(np.float32),
+                        np.array([0.1, np.float32(0.1), 1e-40, -1e-40, 0.0, -0.0, 1.0, -1.0, 3.4e38, -3.4e38,
+                                  np.inf, -np.inf, np.nan], np.float32)])
+    x = np.arange(y.size, dtype=np.int64)
+    dx, dy = torch.from_numpy(x).to("cuda"), torch.from_numpy(y).to("cuda")
+    bounds = [(0.1, 0.5), (np.float32(0.1), 1.0), (1e-41, 1e-39), (-1e-39, 0.0), (0.0, 0.0), (-np.inf, -3e38),
+              (3e38, np.inf), (1e300, None), (None, -1e300), (-0.0, 1.0), (1.0, 1.0)]
+    for lo, hi in bounds:
+        for li in (True, False):
+            for hi_inc in (True, False):
+                m = mask_of(y, lo, hi, li, hi_inc)
+                got = agg.Plan("i64", "sum", max_n=x.size).run_filtered(dx, agg.make_filter(dy, lo, hi, li, hi_inc))
+                assert got["count"] == int(m.sum()), f"[{lo},{hi}] {li} {hi_inc}: count {got['count']} != {m.sum()}"
+                assert got["i64"] == int(x[m].sum()), f"[{lo},{hi}] {li} {hi_inc}"
+    with pytest.raises(agg.AggError):
+        agg.Plan("i64", "sum", max_n=x.size).run_filtered(dx, agg.make_filter(dy, float("nan"), 1.0))
+
+
+def test_integer_bounds_at_the_type_limits(agg):
+    import torch
+    y = np.array([-2**31, -2**31 + 1, -1, 0, 1, 2**31 - 2, 2**31 - 1] * 1000, np.int32)
+    x = np.ones(y.size, np.int32)
+    dx, dy = torch.from_numpy(x).to("cuda"), torch.from_numpy(y).to("cuda")
+    for lo, hi in [(-2**63, 2**63 - 1), (-2**31, -2**31), (2**31 - 1, 2**31 - 1), (2**31, None),
+                   (None, -2**31 - 1), (-2**40, 2**40), (0, 0), (2**63 - 1, None), (None, -2**63)]:
+        for li in (True, False):
+            for hi_inc in (True, False):
+                m = mask_of(y, lo, hi, li, hi_inc)
+                got = agg.Plan("i32", "count", max_n=x.size).run_filtered(dx, agg.make_filter(dy, lo, hi, li, hi_inc))
+                assert got["i64"] == int(m.sum()), f"[{lo},{hi}] {li} {hi_inc}"
