@@ -50,6 +50,11 @@ class OracleResult:
         return self.f64
 
 
+class _Group(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_int64), ("i64", ctypes.c_int64), ("f64", ctypes.c_double),
+                ("count", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -72,6 +77,9 @@ def _load():
         lib.oracle_aggregate.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Result)]
         lib.oracle_aggregate.restype = ctypes.c_int
+        lib.oracle_groupby.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_int64, ctypes.c_int, ctypes.POINTER(_Group), ctypes.c_int64]
+        lib.oracle_groupby.restype = ctypes.c_int64
         _lib = lib
     return _lib
 
@@ -120,3 +128,23 @@ def error_report(estimate: float, exact: float, abs_sum: float) -> dict:
         "abs_norm": (err / abs_sum) if abs_sum != 0 else 0.0,
         "kappa": (abs_sum / abs(exact)) if exact != 0 else float("inf"),
     }
+
+
+def groupby(keys: np.ndarray, vals: np.ndarray, op) -> list:
+    """Group-by aggregate: [(key, i64, f64, count)] in ascending key order
+    (see oracle_groupby in oracle.c)."""
+    keys = np.ascontiguousarray(keys)
+    vals = np.ascontiguousarray(vals)
+    kd, vd = _NP[keys.dtype], _NP[vals.dtype]
+    if kd == F32 or keys.size != vals.size:
+        raise TypeError("int32 / int64 keys and values of the same length")
+    o = OPS[op] if isinstance(op, str) else int(op)
+    n = keys.size
+    lib = _load()
+    ng = lib.oracle_groupby(keys.ctypes.data if n else None, kd, vals.ctypes.data if n else None, vd, n, o, None, 0)
+    if ng < 0:
+        raise ValueError(f"oracle_groupby rc={ng}")
+    out = (_Group * max(1, ng))()
+    ng2 = lib.oracle_groupby(keys.ctypes.data if n else None, kd, vals.ctypes.data if n else None, vd, n, o, out, ng)
+    assert ng2 == ng
+    return [(out[i].key, out[i].i64, out[i].f64, out[i].count) for i in range(ng)]

@@ -258,3 +258,95 @@ int oracle_aggregate(const void* col, int64_t n, int dtype, int op, int nthreads
     free(th);
     return O_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* Group-by: for every distinct key k of keys[0..n), the aggregate of the
+ * values whose key is k (the same per-group definitions as above: integer
+ * SUM mod 2^64, MIN, MAX, COUNT, AVG = RN(RN(SUM)/RN(count)); float SUM
+ * exact then rounded once; float MIN / MAX skip NaN).  Groups come out in
+ * ascending key order.  Plain method: sort the item indices by key, then
+ * fold each run of equal keys. */
+
+typedef struct {
+    int64_t key;
+    int64_t i64;     /* integer SUM / MIN / MAX */
+    double f64;      /* float SUM / MIN / MAX, AVG, integer results converted */
+    int64_t count;
+} oracle_group;
+
+static const void* g_sort_keys;
+static int g_sort_key_dtype;
+
+static int64_t key_at(const void* keys, int dt, int64_t i) {
+    return dt == O_I32 ? (int64_t)((const int32_t*)keys)[i] : ((const int64_t*)keys)[i];
+}
+
+static int cmp_index(const void* a, const void* b) {
+    int64_t ka = key_at(g_sort_keys, g_sort_key_dtype, *(const int64_t*)a);
+    int64_t kb = key_at(g_sort_keys, g_sort_key_dtype, *(const int64_t*)b);
+    return (ka > kb) - (ka < kb);
+}
+
+/* Returns the number of groups (>= 0), or a negative code; at most
+ * max_groups are written (the count returned is the true number). */
+int64_t oracle_groupby(const void* keys, int key_dtype, const void* vals, int val_dtype, int64_t n, int op,
+                       oracle_group* out, int64_t max_groups) {
+    if (n < 0 || (n > 0 && (!keys || !vals)) || (key_dtype != O_I32 && key_dtype != O_I64)) return O_EINVAL;
+    if (val_dtype < O_I32 || val_dtype > O_F32 || op < O_SUM || op > O_AVG) return O_EINVAL;
+    int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!idx) return O_ENOMEM;
+    for (int64_t i = 0; i < n; ++i) idx[i] = i;
+    g_sort_keys = keys;
+    g_sort_key_dtype = key_dtype;
+    qsort(idx, (size_t)n, sizeof(int64_t), cmp_index);
+    int64_t ngroups = 0;
+    int64_t i = 0;
+    while (i < n) {
+        const int64_t k = key_at(keys, key_dtype, idx[i]);
+        int64_t j = i;
+        uint64_t wrap = 0;
+        int64_t imin = INT64_MAX, imax = INT64_MIN;
+        float fmin = NAN, fmax = NAN;
+        superacc sa;
+        sa_init(&sa);
+        for (; j < n && key_at(keys, key_dtype, idx[j]) == k; ++j) {
+            const int64_t r = idx[j];
+            if (val_dtype == O_F32) {
+                const float x = ((const float*)vals)[r];
+                sa_add_float(&sa, x);
+                if (!isnan(x) && (isnan(fmin) || x < fmin)) fmin = x;
+                if (!isnan(x) && (isnan(fmax) || x > fmax)) fmax = x;
+            } else {
+                const int64_t x = item_i64(vals, val_dtype, r);
+                wrap += (uint64_t)x;
+                if (x < imin) imin = x;
+                if (x > imax) imax = x;
+            }
+        }
+        if (ngroups < max_groups && out) {
+            oracle_group* g = &out[ngroups];
+            g->key = k;
+            g->count = j - i;
+            g->i64 = 0;
+            g->f64 = 0.0;
+            if (op == O_COUNT) {
+                g->i64 = j - i;
+                g->f64 = (double)(j - i);
+            } else if (val_dtype == O_F32) {
+                const double s = sa_to_double(&sa);
+                if (op == O_SUM) g->f64 = s;
+                else if (op == O_AVG) g->f64 = s / (double)(j - i);
+                else g->f64 = (double)(op == O_MIN ? fmin : fmax);
+            } else {
+                const int64_t s = (int64_t)wrap;
+                if (op == O_SUM) { g->i64 = s; g->f64 = (double)s; }
+                else if (op == O_AVG) { g->i64 = s; g->f64 = (double)s / (double)(j - i); }
+                else { g->i64 = op == O_MIN ? imin : imax; g->f64 = (double)g->i64; }
+            }
+        }
+        ++ngroups;
+        i = j;
+    }
+    free(idx);
+    return ngroups;
+}

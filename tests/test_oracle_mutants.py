@@ -34,12 +34,21 @@ MUTANTS = {
                                       "(void)carry;\n        }\n    }"),
     "merge_skips_thread": ("if (dtype == O_F32) sa_merge(&m->sa, &jobs[t].sa);",
                            "if (dtype == O_F32 && t != 1) sa_merge(&m->sa, &jobs[t].sa);"),
+    "groupby_run_cut_short": ("for (; j < n && key_at(keys, key_dtype, idx[j]) == k; ++j) {",
+                              "for (; j < n && (j == i || key_at(keys, key_dtype, idx[j - 1]) == k) && key_at(keys, key_dtype, idx[j]) == k && j - i < 5; ++j) {"),
+    "groupby_compare_flipped": ("return (ka > kb) - (ka < kb);", "return (ka < kb) - (ka > kb);"),
+    "groupby_count_off": ("g->count = j - i;", "g->count = j - i + (j == n);"),
 }
 
 
 class _Res(ctypes.Structure):
     _fields_ = [("i64", ctypes.c_int64), ("f64", ctypes.c_double), ("count", ctypes.c_int64),
                 ("is_null", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _Grp(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_int64), ("i64", ctypes.c_int64), ("f64", ctypes.c_double),
+                ("count", ctypes.c_int64)]
 
 
 def _build(src_text: str, path: str):
@@ -51,6 +60,9 @@ def _build(src_text: str, path: str):
     lib = ctypes.CDLL(path)
     lib.oracle_aggregate.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_int, ctypes.POINTER(_Res)]
+    lib.oracle_groupby.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                                   ctypes.c_int, ctypes.POINTER(_Grp), ctypes.c_int64]
+    lib.oracle_groupby.restype = ctypes.c_int64
     return lib
 
 
@@ -98,6 +110,18 @@ def _pin_failures(lib) -> list:
         bad.append("round_up")
     if _agg(lib, big, 2, 4).f64 != float(big.max()) or _agg(lib, big, 1, 4).f64 != float(big.min()):
         bad.append("f32_minmax")
+    # group-by: against a Python dict
+    gk = r.integers(-50, 50, size=5000).astype(np.int64)
+    gv = r.integers(-1000, 1000, size=5000).astype(np.int32)
+    out = (_Grp * 200)()
+    ng = lib.oracle_groupby(gk.ctypes.data, 1, gv.ctypes.data, 0, gk.size, 0, out, 200)
+    want = {}
+    for k, v in zip(gk.tolist(), gv.tolist()):
+        want[k] = want.get(k, 0) + v
+    cnt = {k: int((gk == k).sum()) for k in want}
+    got = [(out[i].key, out[i].i64, out[i].count) for i in range(min(ng, 200))]
+    if ng != len(want) or got != [(k, want[k], cnt[k]) for k in sorted(want)]:
+        bad.append("groupby")
     return bad
 
 
