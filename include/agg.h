@@ -244,6 +244,42 @@ typedef struct agg_filter {
 int agg_run_filtered(agg_plan_t plan, const void* col, int64_t n, const agg_filter* filter,
                      agg_result* out, void* stream);
 
+/* ---- group-by aggregation ---- */
+
+/* For every distinct key k of keys[0..n), the aggregate of the values whose
+ * key is k (the group-by aggregation of the prior GPU work the paper cites,
+ * Section 7).  Per group: integer SUM mod 2^64, MIN, MAX, COUNT and AVG as for
+ * whole columns; float SUM is the exact sum of the group's items rounded
+ * once to double (accumulated in fixed-point digits, so every result is
+ * deterministic and independent of thread order), float AVG divides it by
+ * the count, float MIN / MAX skip NaN.  Groups come out in an unspecified
+ * order. */
+typedef struct agg_group {   /* 32 bytes */
+    int64_t key;
+    int64_t i64;     /* integer SUM / MIN / MAX, COUNT; integer AVG: the SUM */
+    double f64;      /* float results, AVG; integer results converted */
+    int64_t count;   /* items in the group */
+} agg_group;
+
+typedef struct agg_groupby_s* agg_groupby_t;
+
+/* Plan a group-by for int32 / int64 keys and int32 / int64 / float32 values
+ * with up to max_n items and max_groups distinct keys: allocates the device
+ * hash table (2 x max_groups slots rounded up to a power of two; float SUM /
+ * AVG tables carry 12 fixed-point digits per slot).  Float SUM / AVG plans
+ * take at most 2^31 items per run. */
+int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, int32_t op, int64_t max_n,
+                     int64_t max_groups);
+
+/* Group keys[0..n) / vals[0..n) (device memory) on `stream`: writes up to
+ * max_groups groups to groups[] (device memory) and the number of groups to
+ * *ngroups (device or page-locked host memory), or -1 if the input has more
+ * distinct keys than the plan's max_groups.  Never allocates. */
+int agg_groupby_run(agg_groupby_t plan, const void* keys, const void* vals, int64_t n, agg_group* groups,
+                    int64_t* ngroups, void* stream);
+
+int agg_groupby_destroy(agg_groupby_t plan);
+
 /* ---- compressed int32 columns (frame of reference + bit packing) ---- */
 
 /* The paper finds host-to-device transfer to dominate end-to-end time and

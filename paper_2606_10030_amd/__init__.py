@@ -180,6 +180,9 @@ def lib():
                                 ctypes.c_double, ctypes.c_double, ctypes.POINTER(RequestStats),
                                 ctypes.POINTER(ServeSummary)], ctypes.c_int),
         "agg_run_filtered": ([vp, vp, i64, ctypes.POINTER(Filter), vp, vp], ctypes.c_int),
+        "agg_groupby_plan": ([ctypes.POINTER(vp), i32, i32, i32, i64, i64], ctypes.c_int),
+        "agg_groupby_run": ([vp, vp, vp, i64, vp, vp, vp], ctypes.c_int),
+        "agg_groupby_destroy": ([vp], ctypes.c_int),
         "agg_pack_bound": ([i64, ctypes.POINTER(i64)], ctypes.c_int),
         "agg_pack_i32": ([vp, i64, vp, vp, i64, ctypes.POINTER(i64), i32], ctypes.c_int),
         "agg_run_packed": ([vp, ctypes.POINTER(Packed), vp, vp], ctypes.c_int),
@@ -404,6 +407,77 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             lib().agg_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Group(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_int64), ("i64", ctypes.c_int64), ("f64", ctypes.c_double),
+                ("count", ctypes.c_int64)]
+
+
+GROUP_BYTES = ctypes.sizeof(Group)
+assert GROUP_BYTES == 32
+
+
+class GroupBy:
+    """agg_groupby_plan / agg_groupby_run: per-key aggregates of a value column."""
+
+    def __init__(self, key_dtype, val_dtype, op, max_n: int, max_groups: int):
+        self.key_dtype = _code(key_dtype, DTYPES, "dtype")
+        self.val_dtype = _code(val_dtype, DTYPES, "dtype")
+        self.op = _code(op, OPS, "op")
+        self.max_n, self.max_groups = int(max_n), int(max_groups)
+        h = ctypes.c_void_p()
+        _check(lib().agg_groupby_plan(ctypes.byref(h), self.key_dtype, self.val_dtype, self.op, self.max_n,
+                                      self.max_groups), "agg_groupby_plan")
+        self._h = h
+        self._out = None
+        self._ng = None
+
+    def _col(self, col, dtype, what):
+        if isinstance(col, int):
+            return col
+        if _dtype_of_tensor(col) != dtype:
+            raise TypeError(f"{what} dtype {col.dtype} does not match the plan")
+        if not col.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        return col.data_ptr()
+
+    def enqueue(self, keys, vals, groups, ngroups, n: Optional[int] = None, stream=None) -> None:
+        """Enqueue agg_groupby_run; `groups` / `ngroups` are tensors or addresses."""
+        nn = int(n) if n is not None else keys.numel()
+        kp = self._col(keys, self.key_dtype, "keys") if nn else 0
+        vp = self._col(vals, self.val_dtype, "values") if nn else 0
+        gp = groups if isinstance(groups, int) else groups.data_ptr()
+        np_ = ngroups if isinstance(ngroups, int) else ngroups.data_ptr()
+        _check(lib().agg_groupby_run(self._h, kp, vp, nn, gp, np_, _stream_handle(stream)), "agg_groupby_run")
+
+    def run(self, keys, vals, n: Optional[int] = None, stream=None):
+        """Run and wait; returns [(key, i64, f64, count)] sorted by key, or None
+        when the input has more than max_groups distinct keys."""
+        torch = _torch()
+        if self._out is None:
+            self._out = torch.empty(self.max_groups * GROUP_BYTES, dtype=torch.uint8, device="cuda")
+            self._ng = torch.zeros(1, dtype=torch.int64, pin_memory=True)
+        s = torch.cuda.current_stream() if stream is None else stream
+        self.enqueue(keys, vals, self._out, self._ng, n=n, stream=s)
+        s.synchronize()
+        ng = int(self._ng[0])
+        if ng < 0:
+            return None
+        raw = self._out[:ng * GROUP_BYTES].cpu().numpy().tobytes()
+        gs = [Group.from_buffer_copy(raw, i * GROUP_BYTES) for i in range(ng)]
+        return sorted(((g.key, g.i64, g.f64, g.count) for g in gs), key=lambda t: t[0])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().agg_groupby_destroy(self._h)
             self._h = None
 
     def __del__(self):

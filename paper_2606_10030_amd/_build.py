@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libagg.so")
-SOURCES = ["agg_kernels.hip", "agg_api.hip", "agg_tuner.hip", "agg_serve.hip", "agg_pack.hip", "agg_filter.hip"]
+SOURCES = ["agg_kernels.hip", "agg_api.hip", "agg_tuner.hip", "agg_serve.hip", "agg_pack.hip", "agg_filter.hip", "agg_groupby.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

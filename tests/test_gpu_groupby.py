@@ -1,0 +1,185 @@
+"""GPU: group-by aggregation (agg_groupby_run) against the oracle.
+
+The oracle sorts the row indices by key and folds each run (exact float sums
+rounded once); the GPU hashes.  Groups are compared after sorting by key:
+keys, counts and integer results bit for bit, float results exactly (the
+GPU's float sums are exact too).  A float MIN / MAX of a group that holds
+both 0.0 and -0.0 may differ in the zero's sign (both are correct: the two
+compare equal), which the float comparison below allows."""
+import math
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+DTS = ["i32", "i64", "f32"]
+OPS = ["sum", "min", "max", "count", "avg"]
+NP = {"i32": np.int32, "i64": np.int64, "f32": np.float32}
+
+
+@pytest.fixture(scope="module")
+def agg():
+    import torch
+    import paper_2606_10030_amd as agg
+    assert torch.cuda.is_available()
+    return agg
+
+
+def same_float(a: float, b: float) -> bool:
+    return (math.isnan(a) and math.isnan(b)) or a == b
+
+
+def compare(got, want, ctx):
+    assert got is not None, f"{ctx}: reported overflow"
+    assert len(got) == len(want), f"{ctx}: {len(got)} groups != {len(want)}"
+    for g, w in zip(got, want):
+        assert g[0] == w[0] and g[3] == w[3], f"{ctx}: key/count {g} != {w}"
+        assert g[1] == w[1], f"{ctx}: key {w[0]} i64 {g[1]} != {w[1]}"
+        assert same_float(g[2], w[2]), f"{ctx}: key {w[0]} f64 {g[2]!r} != {w[2]!r}"
+
+
+def make_keys(n, kdt, card, seed, dist="uniform"):
+    r = np.random.default_rng(seed)
+    if dist == "zipf":
+        ranks = np.minimum(r.zipf(1.3, size=n), card) - 1
+    else:
+        ranks = r.integers(0, card, size=n)
+    if kdt == "i32":
+        pool = r.choice(2**32, size=card, replace=False).astype(np.int64) - 2**31
+        pool[0] = -2**31
+        if card > 1:
+            pool[1] = 2**31 - 1
+        pool = np.unique(pool)
+        return pool[ranks % pool.size].astype(np.int32)
+    pool = r.integers(-2**63, 2**63 - 1, size=card, dtype=np.int64)
+    pool[0] = -2**63                        # the key that shares the empty-slot bit pattern
+    if card > 1:
+        pool[1] = 2**63 - 1
+    pool = np.unique(pool)
+    return pool[ranks % pool.size].astype(np.int64)
+
+
+def make_vals(n, vdt, seed):
+    if vdt == "f32":
+        r = np.random.default_rng(seed)
+        return (r.standard_normal(n) * np.exp2(r.integers(-40, 41, size=n))).astype(np.float32)
+    return datagen.column(n, vdt, "uniform", seed=seed)
+
+
+def run_case(agg, keys, vals, op, max_groups, ctx):
+    import torch
+    kdt = {np.dtype(np.int32): "i32", np.dtype(np.int64): "i64"}[keys.dtype]
+    vdt = {np.dtype(np.int32): "i32", np.dtype(np.int64): "i64", np.dtype(np.float32): "f32"}[vals.dtype]
+    g = agg.GroupBy(kdt, vdt, op, max_n=max(keys.size, 1), max_groups=max_groups)
+    got = g.run(torch.from_numpy(keys).to("cuda"), torch.from_numpy(vals).to("cuda"))
+    compare(got, oracle.groupby(keys, vals, op), ctx)
+
+
+@pytest.mark.parametrize("vdt", DTS)
+@pytest.mark.parametrize("kdt", ["i32", "i64"])
+def test_groupby_matches_oracle(agg, kdt, vdt):
+    n = 200_003
+    for card in (1, 16, 1000, 50_000):
+        keys = make_keys(n, kdt, card, seed=card)
+        vals = make_vals(n, vdt, seed=card + 1)
+        for op in OPS:
+            run_case(agg, keys, vals, op, max_groups=max(card, 1), ctx=f"{kdt}/{vdt} card={card} {op}")
+
+
+@pytest.mark.parametrize("vdt", DTS)
+def test_groupby_skewed_keys(agg, vdt):
+    """Zipf-distributed keys: a few groups take most rows (LDS contention)."""
+    n = 1_000_003
+    keys = make_keys(n, "i64", 5000, seed=21, dist="zipf")
+    vals = make_vals(n, vdt, seed=22)
+    for op in OPS:
+        run_case(agg, keys, vals, op, max_groups=5000, ctx=f"zipf {vdt} {op}")
+
+
+def test_groupby_many_groups(agg):
+    """More distinct keys than any workgroup's LDS table: the global table path."""
+    n = 3_000_017
+    r = np.random.default_rng(5)
+    keys = r.integers(-2**40, 2**40, size=n, dtype=np.int64) // 4
+    keys = keys % 1_000_003
+    vals = make_vals(n, "f32", seed=6)
+    for op in ("sum", "count", "max"):
+        run_case(agg, keys, vals, op, max_groups=1_000_003, ctx=f"many groups {op}")
+    vals_i = make_vals(n, "i64", seed=7)
+    run_case(agg, keys, vals_i, "sum", max_groups=1_000_003, ctx="many groups i64 sum")
+
+
+def test_groupby_float_specials(agg):
+    import torch
+    keys = np.repeat(np.arange(6, dtype=np.int32), 1000)
+    vals = np.ones(keys.size, np.float32)
+    vals[0] = np.nan                       # group 0: NaN
+    vals[1000] = np.inf                    # group 1: +inf
+    vals[2000] = -np.inf                   # group 2: -inf
+    vals[3000], vals[3001] = np.inf, -np.inf   # group 3: NaN
+    vals[4000:5000] = np.nan               # group 4: every item NaN -> MIN / MAX NaN
+    vals[5000:5500], vals[5500:] = 3.4e38, 3.4e38   # group 5: sum beyond float range, finite in double
+    for op in OPS:
+        run_case(agg, keys, vals, op, max_groups=6, ctx=f"specials {op}")
+    # signed zeros: MIN / MAX compare equal to the oracle's whichever zero they pick
+    z = np.array([0.0, -0.0] * 500, np.float32)
+    g = agg.GroupBy("i32", "f32", "min", max_n=z.size, max_groups=1)
+    got = g.run(torch.zeros(z.size, dtype=torch.int32, device="cuda"), torch.from_numpy(z).to("cuda"))
+    assert got[0][2] == 0.0 and got[0][3] == z.size
+
+
+def test_groupby_float_sum_is_exact(agg):
+    """Cancelling float sums: the exact value rounded once, whatever the order."""
+    n = 400_000
+    r = np.random.default_rng(9)
+    keys = r.integers(0, 7, size=n).astype(np.int32)
+    x = (r.standard_normal(n // 2) * np.exp2(r.integers(-60, 61, size=n // 2))).astype(np.float32)
+    vals = np.concatenate([x, -x])
+    vals[::1001] = np.float32(1e-30)
+    keys = keys[r.permutation(n)]
+    run_case(agg, keys, vals, "sum", max_groups=7, ctx="cancelling sums")
+    run_case(agg, keys, vals, "avg", max_groups=7, ctx="cancelling avg")
+
+
+def test_groupby_overflow_and_limits(agg):
+    import torch
+    keys = np.arange(1000, dtype=np.int64) * 7919
+    vals = np.ones(1000, np.int32)
+    dk, dv = torch.from_numpy(keys).to("cuda"), torch.from_numpy(vals).to("cuda")
+    assert agg.GroupBy("i64", "i32", "sum", max_n=1000, max_groups=999).run(dk, dv) is None
+    assert agg.GroupBy("i64", "i32", "sum", max_n=1000, max_groups=400).run(dk, dv) is None
+    assert agg.GroupBy("i64", "i32", "sum", max_n=1000, max_groups=10).run(dk, dv) is None
+    got = agg.GroupBy("i64", "i32", "sum", max_n=1000, max_groups=1000).run(dk, dv)
+    assert [g[0] for g in got] == sorted(keys.tolist()) and all(g[1] == 1 for g in got)
+
+
+def test_groupby_empty_and_reuse(agg):
+    import torch
+    g = agg.GroupBy("i32", "i64", "sum", max_n=100_000, max_groups=100)
+    e = torch.empty(0, dtype=torch.int32, device="cuda")
+    assert g.run(e, torch.empty(0, dtype=torch.int64, device="cuda")) == []
+    for n, seed in ((100_000, 1), (5000, 2), (1, 3), (0, 4), (77_777, 5)):
+        keys = make_keys(n, "i32", 100, seed=seed) if n else np.zeros(0, np.int32)
+        vals = make_vals(n, "i64", seed=seed)
+        got = g.run(torch.from_numpy(keys).to("cuda"), torch.from_numpy(vals).to("cuda"), n=n)
+        compare(got, oracle.groupby(keys, vals, "sum"), f"reuse n={n}")
+
+
+def test_groupby_errors(agg):
+    import torch
+    with pytest.raises(agg.AggError):
+        agg.GroupBy("f32", "i32", "sum", max_n=10, max_groups=10)     # float keys
+    with pytest.raises(agg.AggError):
+        agg.GroupBy("i32", "i32", "sum", max_n=10, max_groups=0)
+    with pytest.raises(agg.AggError):
+        agg.GroupBy("i32", "f32", "sum", max_n=2**31 + 1, max_groups=10)   # float digit headroom
+    g = agg.GroupBy("i32", "i32", "sum", max_n=100, max_groups=10)
+    k = torch.zeros(200, dtype=torch.int32, device="cuda")
+    with pytest.raises(agg.AggError):
+        g.run(k, k, n=200)                                                    # beyond max_n
+    with pytest.raises(agg.AggError):
+        g.run(np.zeros(10, np.int32).ctypes.data, k, n=10)                    # pageable host keys
