@@ -8,8 +8,8 @@ reads items; COUNT reads none) divided by the step time.
 
 Also reported, outside the timed steps: the per-cell GB/s and roofline
 fraction, the dominant kernel's roofline (HIP events over the timed region),
-the plain and f64-combine float modes, the 2^20-item int32 SUM latency, the
-end-to-end rate from pinned host memory (chunked copy pipeline and zero-copy)
+the plain and f64-combine float modes, the fused filter, group-by over 2^28
+rows, the 2^20-item int32 SUM latency, the end-to-end rate from pinned host memory (chunked copy pipeline and zero-copy)
 with the measured host-to-device copy ceiling, and the CPU oracle's rate on
 one step's worth of the same cells (cpu_baseline).
 
@@ -217,6 +217,38 @@ def bench_batch(agg, torch, stream, table):
     return out
 
 
+def bench_groupby(agg, torch, stream, dev):
+    """Group-by over 2^28 rows: int32 keys of a given number of distinct values
+    (a multiplicative hash of the uniform int32 column, reduced mod the
+    cardinality) with int64 or float32 values.  Bytes = keys + values read once."""
+    n = 1 << 28
+    out = {}
+    for card in (16, 1024, 1 << 16, 1 << 20):
+        keys = torch.remainder(dev["i32"][:n].to(torch.int64) * 2654435761, card).to(torch.int32)
+        for vdt, op in (("i64", "sum"), ("f32", "sum"), ("i32", "count")):
+            g = agg.GroupBy("i32", vdt, op, max_n=n, max_groups=card)
+            groups = torch.empty(card * agg.GROUP_BYTES, dtype=torch.uint8, device="cuda")
+            ng = torch.zeros(1, dtype=torch.int64, device="cuda")
+            vals = dev[vdt][:n]
+            for _ in range(2):
+                g.enqueue(keys, vals, groups, ng, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(5):
+                g.enqueue(keys, vals, groups, ng, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 5
+            b = n * (4 + (0 if op == "count" else WIDTH[vdt]))
+            out[f"{op}_{vdt}_by_i32_card{card}"] = {
+                "ms": round(ms, 4), "GB/s": round(b / (ms * 1e-3) / 1e9, 1),
+                "Grows/s": round(n / (ms * 1e-3) / 1e9, 2), "hbm_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "groups": int(ng.item())}
+            g.close()
+        del keys
+    return out
+
+
 def bench_serve(agg, torch, host_i32, dev_i32, full=False):
     """Poisson stream of int32 requests, lengths log-uniform in [1e4, n_max],
     30% resident (slices of a column in HBM) and 70% shipped from pinned host
@@ -271,6 +303,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-energy", action="store_true")
+    ap.add_argument("--no-groupby", action="store_true")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving with 10^4 requests of up to 2^33 int32 items (minutes of PCIe time)")
     ap.add_argument("--n", type=int, default=N_ITEMS, help=argparse.SUPPRESS)
@@ -422,6 +455,10 @@ def main():
     torch.cuda.synchronize()
     extra["i32_sum_2e20_us_per_call"] = round(e0.elapsed_time(e1) / 200 * 1e3, 2)
     p.close()
+
+    # ---- group-by aggregation (per-key SUM / COUNT over 2^28 rows)
+    if not args.no_groupby:
+        extra["groupby"] = bench_groupby(agg, torch, stream, dev)
 
     # ---- end to end from pinned host memory
     if not args.no_e2e:

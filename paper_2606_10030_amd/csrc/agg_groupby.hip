@@ -4,21 +4,33 @@
 // Table: open addressing over a power-of-two number of slots, keys claimed
 // with a 64-bit compare-and-swap (INT64_MIN marks an empty slot; the key
 // INT64_MIN itself lives in one extra slot), linear probing bounded by the
-// table size -- no thread ever waits on another.  Each workgroup first
-// aggregates into its own table in LDS (a few probes per item; items whose
-// key finds no LDS slot go straight to the global table) and flushes the
-// LDS table once at the end, so low-cardinality inputs cost LDS atomics
-// rather than contended global ones.
+// table size -- no thread ever waits on another.  Rows are first aggregated
+// into a workgroup's own table in LDS (a few probes per row; a row whose key
+// finds no LDS slot goes straight to the global table) and each LDS table is
+// flushed into the global table once, so the global table sees one update
+// per (workgroup, key) instead of one per row.
+//
+// Two paths, chosen from the plan's max_groups:
+//  * direct: every workgroup's LDS table can hold all the groups; workgroups
+//    stride over the rows.
+//  * partitioned (more groups than an LDS table holds): rows are processed in
+//    chunks; each chunk is radix-partitioned on the top bits of the key's
+//    hash (histogram, prefix sums, scatter into a staging copy), so that one
+//    partition has few enough distinct keys for an LDS table, and then one
+//    workgroup (or several, for a partition with many rows) aggregates each
+//    partition in LDS.
 //
 // Determinism: integer SUM (mod 2^64), MIN, MAX and COUNT are exact in any
-// order.  A float32 SUM is accumulated exactly: every float is m * 2^(k-149)
-// with m < 2^24, added as two integer digits of a base-2^32 fixed-point
-// number (12 digits per group), so the group sum is exact whatever the order
-// and is rounded once to double at the end.
+// order.  A float32 SUM is accumulated exactly: every finite float is
+// m * 2^(k-149) with m < 2^24, added as two integer digits of a base-2^32
+// fixed-point number, so the group sum is exact whatever the order and is
+// rounded once to double at the end.  The row order inside a partition (set
+// by LDS atomics) therefore never shows in a result.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <new>
+#include <type_traits>
 
 #include "agg.h"
 #include "agg_internal.hpp"
@@ -27,11 +39,25 @@ namespace agg {
 namespace gb {
 
 constexpr int64_t kEmpty = INT64_MIN;
-constexpr int kDigits = 12;
+constexpr int kDigits = 9;            // digits a float lands in: k/32 <= 7, plus one
+constexpr int kNormDigits = 11;       // after carries (|sum| < 2^31 * 2^128 * 2^149)
 constexpr int kThreads = 256;
 constexpr int kLdsProbes = 16;
+constexpr int kAggRows = 8;           // rows whose loads a thread keeps in flight
+constexpr int kMaxPartBits = 14;      // at most 16384 partitions
+constexpr int64_t kChunkRows = (int64_t)1 << 26;
+constexpr int64_t kHistRows = (int64_t)1 << 16;    // rows per histogram / scatter workgroup
+constexpr int kMaxHistWg = (int)(kChunkRows / kHistRows);
+constexpr int kScanThreads = 1024;
+constexpr int kTileThreads = 1024;    // tiled scatter: rows staged in LDS per tile
+constexpr int kTileRows = 8192;
+constexpr int kTileMaxBits = 9;       // tiled scatter for up to 512 partitions
 
 enum GOp { G_COUNT = 0, G_SUM_INT, G_MIN_INT, G_MAX_INT, G_SUM_F32, G_MIN_F32, G_MAX_F32 };
+
+template <int G>
+constexpr int lds_slots() { return G == G_SUM_F32 ? 512 : 2048; }
+inline int lds_slots_of(int g) { return g == G_SUM_F32 ? 512 : 2048; }
 
 struct Table {
   int64_t* key;        // cap + 1 slots; slot cap holds the key INT64_MIN
@@ -43,9 +69,22 @@ struct Table {
   int64_t cap;
 };
 
+// Radix partitioning of one chunk of rows.
+struct Part {
+  uint32_t* hist;      // [P][g1]: rows of partition p in scatter workgroup g, then their prefix
+  uint32_t* tot;       // [P] rows per partition
+  uint32_t* start;     // [P + 1] first staged row of each partition
+  void* pk;            // staged keys (kChunkRows)
+  void* pv;            // staged values (none for COUNT)
+  int32_t bits;        // log2 of the number of partitions
+  int32_t g1;          // histogram / scatter workgroups of this chunk
+  int64_t rows_per_wg; // rows each of them covers
+};
+
 struct Args {
   Table t;
-  const void* keys;
+  Part pt;
+  const void* keys;    // this launch's rows (a chunk in the partitioned path)
   const void* vals;
   int64_t n;
   agg_group* out;
@@ -59,8 +98,6 @@ template <int G>
 constexpr int64_t val_identity() {
   return (G == G_MIN_INT || G == G_MIN_F32) ? INT64_MAX : (G == G_MAX_INT || G == G_MAX_F32) ? INT64_MIN : 0;
 }
-template <int G>
-constexpr int lds_slots() { return G == G_SUM_F32 ? 256 : 2048; }
 
 __device__ __forceinline__ uint64_t mix64(uint64_t k) {  // MurmurHash3's 64-bit finaliser
   k ^= k >> 33;
@@ -71,6 +108,11 @@ __device__ __forceinline__ uint64_t mix64(uint64_t k) {  // MurmurHash3's 64-bit
   return k;
 }
 
+// Partition of a key: the top bits of its hash (table slots use the low bits).
+__device__ __forceinline__ uint32_t part_of(int64_t k, int bits) {
+  return (uint32_t)(mix64((uint64_t)k) >> (64 - bits));
+}
+
 // Order-preserving map of non-NaN floats to int32 (and back).
 __device__ __forceinline__ int32_t f32_order(float f) {
   const int32_t b = __float_as_int(f);
@@ -78,7 +120,7 @@ __device__ __forceinline__ int32_t f32_order(float f) {
 }
 __device__ __forceinline__ float f32_unorder(int32_t o) { return __int_as_float(o >= 0 ? o : (o ^ 0x7FFFFFFF)); }
 
-// The two fixed-point digits of a finite float (value = sum d[k] 2^(32k) 2^-149).
+// The two fixed-point digits of a finite float (value = sum d[j] 2^(32j) 2^-149).
 __device__ __forceinline__ void f32_digits(float x, int* k0, int64_t* lo, int64_t* hi) {
   const uint32_t bits = __float_as_uint(x);
   const uint32_t biased = (bits >> 23) & 0xFFu, frac = bits & 0x7FFFFFu;
@@ -106,7 +148,7 @@ __device__ __forceinline__ int64_t load_ival(const void* p, int64_t i) {
   else return static_cast<const int64_t*>(p)[i];
 }
 
-// Fold one item into a slot (LDS or global: the pointers decide).
+// Fold one row into a slot (LDS or global: the pointers decide).
 template <int G>
 __device__ __forceinline__ void apply(uint64_t* cnt, int64_t* val, int64_t* dig, int32_t* flags, int64_t iv,
                                       float fv) {
@@ -159,74 +201,335 @@ __device__ __forceinline__ void apply_global(const Table& t, int64_t s, int64_t 
   apply<G>(t.cnt + s, t.val + s, t.dig + (G == G_SUM_F32 ? s * kDigits : 0), t.flags + s, iv, fv);
 }
 
-template <int KD, int VD, int G>
-__global__ void __launch_bounds__(kThreads) gb_aggregate_kernel(Args a) {
-  constexpr int L = lds_slots<G>();
-  constexpr bool kDig = G == G_SUM_F32;
-  __shared__ int64_t lkey[L];
-  __shared__ uint64_t lcnt[L];
-  __shared__ int64_t lval[kDig ? 1 : L];
-  __shared__ int64_t ldig[kDig ? L * kDigits : 1];
-  __shared__ int32_t lflags[kDig ? L : 1];
-  const Table& t = a.t;
-  for (int e = threadIdx.x; e < L; e += kThreads) {
-    lkey[e] = kEmpty;
-    lcnt[e] = 0;
-    if constexpr (!kDig) lval[e] = val_identity<G>();
-    if constexpr (kDig) {
-      lflags[e] = 0;
-      for (int d = 0; d < kDigits; ++d) ldig[e * kDigits + d] = 0;
+// ---- histogram / prefix sums / scatter of the partitioned path ----
+
+template <int KD>
+__global__ void __launch_bounds__(kThreads) gb_hist_kernel(Args a) {
+  extern __shared__ uint32_t h[];
+  const int P = 1 << a.pt.bits;
+  for (int e = threadIdx.x; e < P; e += kThreads) h[e] = 0;
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * a.pt.rows_per_wg;
+  const int64_t hi = std::min<int64_t>(lo + a.pt.rows_per_wg, a.n);
+  for (int64_t base = lo + threadIdx.x; base < hi; base += kThreads * kAggRows) {
+    int64_t kk[kAggRows];
+#pragma unroll
+    for (int r = 0; r < kAggRows; ++r) {
+      const int64_t i = base + (int64_t)r * kThreads;
+      kk[r] = i < hi ? load_key<KD>(a.keys, i) : 0;
     }
+#pragma unroll
+    for (int r = 0; r < kAggRows; ++r)
+      if (base + (int64_t)r * kThreads < hi) atomicAdd(&h[part_of(kk[r], a.pt.bits)], 1u);
   }
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * kThreads;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < a.n; i += stride) {
-    const int64_t k = load_key<KD>(a.keys, i);
-    int64_t iv = 0;
-    float fv = 0.0f;
-    if constexpr (G != G_COUNT) {
-      if constexpr (VD == AGG_F32) fv = static_cast<const float*>(a.vals)[i];
-      else iv = load_ival<VD>(a.vals, i);
+  for (int e = threadIdx.x; e < P; e += kThreads) a.pt.hist[(int64_t)e * a.pt.g1 + blockIdx.x] = h[e];
+}
+
+// One wave per partition: exclusive prefix of its per-workgroup counts, in place.
+__global__ void __launch_bounds__(kThreads) gb_scan_rows_kernel(Args a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * (kThreads / 64) + threadIdx.x / 64;
+  if (p >= ((int64_t)1 << a.pt.bits)) return;  // whole waves leave together
+  uint32_t* row = a.pt.hist + p * a.pt.g1;
+  const int q = (a.pt.g1 + 63) / 64;
+  uint32_t s = 0;
+  for (int j = 0; j < q; ++j) {
+    const int idx = lane * q + j;
+    if (idx < a.pt.g1) s += row[idx];
+  }
+  uint32_t incl = s;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  uint32_t run = incl - s;
+  for (int j = 0; j < q; ++j) {
+    const int idx = lane * q + j;
+    if (idx < a.pt.g1) {
+      const uint32_t v = row[idx];
+      row[idx] = run;
+      run += v;
     }
-    int s = -1;
-    if (k != kEmpty) {
-      int h = (int)(mix64((uint64_t)k) & (L - 1));
-      for (int p = 0; p < kLdsProbes; ++p, h = (h + 1) & (L - 1)) {
-        const int64_t cur = lkey[h];
-        if (cur == k) { s = h; break; }
-        if (cur == kEmpty) {
-          const int64_t prev = (int64_t)atomicCAS(reinterpret_cast<unsigned long long*>(&lkey[h]),
-                                                  (unsigned long long)kEmpty, (unsigned long long)k);
-          if (prev == kEmpty || prev == k) { s = h; break; }
+  }
+  if (lane == 63) a.pt.tot[p] = incl;
+}
+
+// One workgroup: partition starts, the exclusive prefix of the totals.
+__global__ void __launch_bounds__(kScanThreads) gb_scan_tot_kernel(Args a) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  const int P = 1 << a.pt.bits;
+  const int q = (P + kScanThreads - 1) / kScanThreads;
+  const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
+  uint32_t sum = 0;
+  for (int j = 0; j < q; ++j) {
+    const int idx = threadIdx.x * q + j;
+    if (idx < P) sum += a.pt.tot[idx];
+  }
+  uint32_t incl = sum;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t run = incl - sum;
+  for (int v = 0; v < w; ++v) run += wsum[v];
+  for (int j = 0; j < q; ++j) {
+    const int idx = threadIdx.x * q + j;
+    if (idx < P) {
+      a.pt.start[idx] = run;
+      run += a.pt.tot[idx];
+    }
+  }
+  if (threadIdx.x == kScanThreads - 1) a.pt.start[P] = run;  // the last thread ends on the total
+}
+
+// The same rows per workgroup as the histogram: each row lands at its
+// partition's start + this workgroup's prefix + a slot taken by an LDS atomic.
+template <int KD, int VD, bool HASV>
+__global__ void __launch_bounds__(kThreads) gb_scatter_kernel(Args a) {
+  extern __shared__ uint32_t cur[];
+  const int P = 1 << a.pt.bits;
+  for (int e = threadIdx.x; e < P; e += kThreads)
+    cur[e] = a.pt.start[e] + a.pt.hist[(int64_t)e * a.pt.g1 + blockIdx.x];
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * a.pt.rows_per_wg;
+  const int64_t hi = std::min<int64_t>(lo + a.pt.rows_per_wg, a.n);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+    const int64_t k = load_key<KD>(a.keys, i);
+    const uint32_t pos = atomicAdd(&cur[part_of(k, a.pt.bits)], 1u);
+    if ((int64_t)pos >= a.n) continue;  // cannot happen: counts match the histogram
+    if constexpr (KD == AGG_I32) static_cast<int32_t*>(a.pt.pk)[pos] = (int32_t)k;
+    else static_cast<int64_t*>(a.pt.pk)[pos] = k;
+    if constexpr (HASV) {
+      if constexpr (VD == AGG_I64) static_cast<int64_t*>(a.pt.pv)[pos] = static_cast<const int64_t*>(a.vals)[i];
+      else static_cast<uint32_t*>(a.pt.pv)[pos] = static_cast<const uint32_t*>(a.vals)[i];
+    }
+  }
+}
+
+// Scatter through LDS: each tile of kTileRows rows is counting-sorted by
+// partition in LDS first, so the rows of one partition leave as one
+// contiguous run (coalesced stores) instead of one scattered store per row.
+template <int KD, int VD, bool HASV>
+__global__ void __launch_bounds__(kTileThreads) gb_scatter_tiled_kernel(Args a) {
+  using KT = typename std::conditional<KD == AGG_I32, int32_t, int64_t>::type;
+  using VT = typename std::conditional<VD == AGG_I64, int64_t, uint32_t>::type;
+  constexpr int R = kTileRows / kTileThreads;
+  constexpr int PM = 1 << kTileMaxBits;
+  __shared__ KT skey[kTileRows];
+  __shared__ VT sval[HASV ? kTileRows : 1];
+  __shared__ uint16_t spart[kTileRows];
+  __shared__ uint32_t tcnt[PM], toff[PM], cur[PM];
+  const int P = 1 << a.pt.bits;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < P; e += kTileThreads) {
+    cur[e] = a.pt.start[e] + a.pt.hist[(int64_t)e * a.pt.g1 + blockIdx.x];
+    tcnt[e] = 0;
+  }
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * a.pt.rows_per_wg;
+  const int64_t hi = std::min<int64_t>(lo + a.pt.rows_per_wg, a.n);
+  for (int64_t t0 = lo; t0 < hi; t0 += kTileRows) {
+    const int rows = (int)std::min<int64_t>(kTileRows, hi - t0);
+    KT k[R];
+    VT v[R];
+    uint32_t pp[R], rank[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = r * kTileThreads + tid;
+      if (j < rows) {
+        k[r] = static_cast<const KT*>(a.keys)[t0 + j];
+        if constexpr (HASV) v[r] = static_cast<const VT*>(a.vals)[t0 + j];
+        pp[r] = part_of((int64_t)k[r], a.pt.bits);
+        rank[r] = atomicAdd(&tcnt[pp[r]], 1u);
+      }
+    }
+    __syncthreads();
+    if (tid < 64) {  // one wave: exclusive prefix of the tile's counts
+      const int q = (P + 63) / 64;
+      uint32_t sum = 0;
+      for (int j = 0; j < q; ++j) sum += (tid * q + j < P) ? tcnt[tid * q + j] : 0u;
+      uint32_t incl = sum;
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (tid >= off) incl += y;
+      }
+      uint32_t run = incl - sum;
+      for (int j = 0; j < q; ++j) {
+        const int e = tid * q + j;
+        if (e < P) {
+          toff[e] = run;
+          run += tcnt[e];
         }
       }
     }
-    if (s >= 0) {
-      apply<G>(&lcnt[s], kDig ? nullptr : &lval[s], kDig ? &ldig[s * kDigits] : nullptr,
-               kDig ? &lflags[s] : nullptr, iv, fv);
-    } else {
-      const int64_t g = global_slot(t, k);
-      if (g >= 0) apply_global<G>(t, g, iv, fv);
-    }
-  }
-  __syncthreads();
-  // flush this workgroup's LDS table into the global table
-  for (int e = threadIdx.x; e < L; e += kThreads) {
-    const int64_t k = lkey[e];
-    if (k == kEmpty) continue;
-    const int64_t g = global_slot(t, k);
-    if (g < 0) continue;
-    atomicAdd(reinterpret_cast<unsigned long long*>(t.cnt + g), (unsigned long long)lcnt[e]);
-    if constexpr (G == G_SUM_INT) atomicAdd(reinterpret_cast<unsigned long long*>(t.val + g), (unsigned long long)lval[e]);
-    if constexpr (G == G_MIN_INT || G == G_MIN_F32) atomicMin(reinterpret_cast<long long*>(t.val + g), (long long)lval[e]);
-    if constexpr (G == G_MAX_INT || G == G_MAX_F32) atomicMax(reinterpret_cast<long long*>(t.val + g), (long long)lval[e]);
-    if constexpr (kDig) {
-      if (lflags[e]) atomicOr(t.flags + g, lflags[e]);
-      for (int d = 0; d < kDigits; ++d) {
-        const int64_t v = ldig[e * kDigits + d];
-        if (v) atomicAdd(reinterpret_cast<unsigned long long*>(t.dig + g * kDigits + d), (unsigned long long)v);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = r * kTileThreads + tid;
+      if (j < rows) {
+        const uint32_t d = toff[pp[r]] + rank[r];
+        skey[d] = k[r];
+        if constexpr (HASV) sval[d] = v[r];
+        spart[d] = (uint16_t)pp[r];
       }
     }
+    __syncthreads();
+    for (int j = tid; j < rows; j += kTileThreads) {
+      const uint32_t q = spart[j];
+      const uint32_t pos = cur[q] + (uint32_t)j - toff[q];
+      if ((int64_t)pos >= a.n) continue;  // cannot happen: counts match the histogram
+      static_cast<KT*>(a.pt.pk)[pos] = skey[j];
+      if constexpr (HASV) static_cast<VT*>(a.pt.pv)[pos] = sval[j];
+    }
+    __syncthreads();
+    for (int e = tid; e < P; e += kTileThreads) {
+      cur[e] += tcnt[e];
+      tcnt[e] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- aggregation into LDS tables, flushed into the global table ----
+
+template <int G>
+struct LdsTable {
+  static constexpr int L = lds_slots<G>();
+  static constexpr bool kDig = G == G_SUM_F32;
+  int64_t key[L];
+  uint64_t cnt[L];
+  int64_t val[kDig ? 1 : L];
+  int64_t dig[kDig ? L * kDigits : 1];
+  int32_t flags[kDig ? L : 1];
+
+  __device__ void clear() {
+    for (int e = threadIdx.x; e < L; e += kThreads) {
+      key[e] = kEmpty;
+      cnt[e] = 0;
+      if constexpr (!kDig) val[e] = val_identity<G>();
+      if constexpr (kDig) {
+        flags[e] = 0;
+        for (int d = 0; d < kDigits; ++d) dig[e * kDigits + d] = 0;
+      }
+    }
+  }
+
+  // Rows first, first + step, ... below last; a row whose key finds no slot
+  // within kLdsProbes goes to the global table.
+  template <int KD, int VD>
+  __device__ void fold_rows(const Table& t, const void* keys, const void* vals, int64_t first, int64_t last,
+                            int64_t step) {
+    constexpr int R = kAggRows;
+    for (int64_t base = first; base < last; base += step * R) {
+      int64_t kk[R], ivv[R];  // R rows' loads in flight before any is folded
+      float fvv[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t i = base + r * step;
+        kk[r] = kEmpty;
+        ivv[r] = 0;
+        fvv[r] = 0.0f;
+        if (i < last) {
+          kk[r] = load_key<KD>(keys, i);
+          if constexpr (G != G_COUNT) {
+            if constexpr (VD == AGG_F32) fvv[r] = static_cast<const float*>(vals)[i];
+            else ivv[r] = load_ival<VD>(vals, i);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (base + r * step >= last) break;
+        const int64_t k = kk[r];
+        int s = -1;
+        if (k != kEmpty) {
+          int h = (int)(mix64((uint64_t)k) & (L - 1));
+          for (int p = 0; p < kLdsProbes; ++p, h = (h + 1) & (L - 1)) {
+            const int64_t cur = key[h];
+            if (cur == k) { s = h; break; }
+            if (cur == kEmpty) {
+              const int64_t prev = (int64_t)atomicCAS(reinterpret_cast<unsigned long long*>(&key[h]),
+                                                      (unsigned long long)kEmpty, (unsigned long long)k);
+              if (prev == kEmpty || prev == k) { s = h; break; }
+            }
+          }
+        }
+        if (s >= 0) {
+          apply<G>(&cnt[s], kDig ? nullptr : &val[s], kDig ? &dig[s * kDigits] : nullptr,
+                   kDig ? &flags[s] : nullptr, ivv[r], fvv[r]);
+        } else {
+          const int64_t g = global_slot(t, k);
+          if (g >= 0) apply_global<G>(t, g, ivv[r], fvv[r]);
+        }
+      }
+    }
+  }
+
+  __device__ void flush(const Table& t) {
+    for (int e = threadIdx.x; e < L; e += kThreads) {
+      const int64_t k = key[e];
+      if (k == kEmpty) continue;
+      const int64_t g = global_slot(t, k);
+      if (g < 0) continue;
+      atomicAdd(reinterpret_cast<unsigned long long*>(t.cnt + g), (unsigned long long)cnt[e]);
+      if constexpr (G == G_SUM_INT) atomicAdd(reinterpret_cast<unsigned long long*>(t.val + g), (unsigned long long)val[e]);
+      if constexpr (G == G_MIN_INT || G == G_MIN_F32) atomicMin(reinterpret_cast<long long*>(t.val + g), (long long)val[e]);
+      if constexpr (G == G_MAX_INT || G == G_MAX_F32) atomicMax(reinterpret_cast<long long*>(t.val + g), (long long)val[e]);
+      if constexpr (kDig) {
+        if (flags[e]) atomicOr(t.flags + g, flags[e]);
+        for (int d = 0; d < kDigits; ++d) {
+          const int64_t v = dig[e * kDigits + d];
+          if (v) atomicAdd(reinterpret_cast<unsigned long long*>(t.dig + g * kDigits + d), (unsigned long long)v);
+        }
+      }
+    }
+  }
+};
+
+// Direct path: every workgroup sweeps the rows grid-stride into one LDS table.
+template <int KD, int VD, int G>
+__global__ void __launch_bounds__(kThreads) gb_aggregate_kernel(Args a) {
+  __shared__ LdsTable<G> tab;
+  tab.clear();
+  __syncthreads();
+  tab.template fold_rows<KD, VD>(a.t, a.keys, a.vals, (int64_t)blockIdx.x * kThreads + threadIdx.x, a.n,
+                                 (int64_t)gridDim.x * kThreads);
+  __syncthreads();
+  tab.flush(a.t);
+}
+
+// Partitioned path: workgroup w takes the w-th equal share of the staged rows
+// and folds it partition by partition, flushing its LDS table at each
+// partition boundary (a partition's keys fit one table; the next partition's
+// keys are all different).  Equal shares keep every workgroup equally busy
+// whatever the partition sizes.
+template <int KD, int VD, int G>
+__global__ void __launch_bounds__(kThreads) gb_aggregate_part_kernel(Args a) {
+  __shared__ LdsTable<G> tab;
+  const int P = 1 << a.pt.bits;
+  int64_t r = a.n * (int64_t)blockIdx.x / gridDim.x;
+  const int64_t r1 = a.n * ((int64_t)blockIdx.x + 1) / gridDim.x;
+  if (r >= r1) return;  // the whole workgroup leaves together
+  int lo = 0, hi = P - 1;  // the partition holding row r: the last p with start[p] <= r
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if ((int64_t)a.pt.start[mid] <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  int p = lo;
+  while (r < r1) {
+    while ((int64_t)a.pt.start[p + 1] <= r) ++p;  // skip partitions that end before r
+    const int64_t seg_end = std::min<int64_t>(r1, (int64_t)a.pt.start[p + 1]);
+    tab.clear();
+    __syncthreads();
+    tab.template fold_rows<KD, VD>(a.t, a.pt.pk, a.pt.pv, r + threadIdx.x, seg_end, kThreads);
+    __syncthreads();
+    tab.flush(a.t);
+    __syncthreads();
+    r = seg_end;
   }
 }
 
@@ -249,17 +552,17 @@ __device__ double digits_to_double(const int64_t* src, int32_t flags) {
   if ((flags & 1) || ((flags & 2) && (flags & 4))) return __builtin_nan("");
   if (flags & 2) return __builtin_inf();
   if (flags & 4) return -__builtin_inf();
-  int64_t d[kDigits];
-  for (int k = 0; k < kDigits; ++k) d[k] = src[k];
-  for (int k = 0; k < kDigits - 1; ++k) {  // carries: digits 0..10 into [0, 2^32)
+  int64_t d[kNormDigits];
+  for (int k = 0; k < kNormDigits; ++k) d[k] = k < kDigits ? src[k] : 0;
+  for (int k = 0; k < kNormDigits - 1; ++k) {  // carries: digits 0..9 into [0, 2^32)
     const int64_t c = d[k] >> 32;
     d[k] -= c * 4294967296ll;
     d[k + 1] += c;
   }
-  const bool neg = d[kDigits - 1] < 0;
+  const bool neg = d[kNormDigits - 1] < 0;
   if (neg) {
-    for (int k = 0; k < kDigits; ++k) d[k] = -d[k];
-    for (int k = 0; k < kDigits - 1; ++k) {
+    for (int k = 0; k < kNormDigits; ++k) d[k] = -d[k];
+    for (int k = 0; k < kNormDigits - 1; ++k) {
       const int64_t c = d[k] >> 32;
       d[k] -= c * 4294967296ll;
       d[k + 1] += c;
@@ -267,7 +570,7 @@ __device__ double digits_to_double(const int64_t* src, int32_t flags) {
   }
   auto bit = [&](int b) -> uint64_t { return (uint64_t)(d[b >> 5] >> (b & 31)) & 1u; };
   int top = -1;
-  for (int b = 32 * kDigits - 1; b >= 0; --b)
+  for (int b = 32 * kNormDigits - 1; b >= 0; --b)
     if (bit(b)) { top = b; break; }
   if (top < 0) return 0.0;
   uint64_t mant = 0;
@@ -319,7 +622,7 @@ __global__ void __launch_bounds__(kThreads) gb_emit_kernel(Args a) {
     } else if constexpr (G == G_SUM_F32) {
       const double sum = digits_to_double(t.dig + s * kDigits, t.flags[s]);
       g.f64 = a.is_avg ? sum / (double)g.count : sum;
-    } else {  // float MIN / MAX: NaN when every item of the group is NaN
+    } else {  // float MIN / MAX: NaN when every row of the group is NaN
       const int64_t v = t.val[s];
       g.f64 = v == val_identity<G>() ? (double)__builtin_nanf("") : (double)f32_unorder((int32_t)v);
     }
@@ -334,6 +637,8 @@ __global__ void gb_finish_kernel(Args a) {
   }
 }
 
+// ---- kernel tables ----
+
 int gop_of(int32_t val_dtype, int32_t op) {
   if (op == AGG_COUNT) return G_COUNT;
   const bool f = val_dtype == AGG_F32;
@@ -343,35 +648,58 @@ int gop_of(int32_t val_dtype, int32_t op) {
   return -1;
 }
 
-template <int KD, int VD>
+template <int KD, int VD, bool PART>
 const void* agg_row(int g) {
+#define GB_AGG(GG)                                                                           \
+  (PART ? reinterpret_cast<const void*>(&gb_aggregate_part_kernel<KD, VD, GG>)               \
+        : reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, GG>))
   if constexpr (VD == AGG_F32) {
     switch (g) {
-      case G_COUNT: return reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, G_COUNT>);
-      case G_SUM_F32: return reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, G_SUM_F32>);
-      case G_MIN_F32: return reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, G_MIN_F32>);
-      case G_MAX_F32: return reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, G_MAX_F32>);
+      case G_COUNT: return GB_AGG(G_COUNT);
+      case G_SUM_F32: return GB_AGG(G_SUM_F32);
+      case G_MIN_F32: return GB_AGG(G_MIN_F32);
+      case G_MAX_F32: return GB_AGG(G_MAX_F32);
       default: return nullptr;
     }
   } else {
     switch (g) {
-      case G_COUNT: return reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, G_COUNT>);
-      case G_SUM_INT: return reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, G_SUM_INT>);
-      case G_MIN_INT: return reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, G_MIN_INT>);
-      case G_MAX_INT: return reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, G_MAX_INT>);
+      case G_COUNT: return GB_AGG(G_COUNT);
+      case G_SUM_INT: return GB_AGG(G_SUM_INT);
+      case G_MIN_INT: return GB_AGG(G_MIN_INT);
+      case G_MAX_INT: return GB_AGG(G_MAX_INT);
       default: return nullptr;
     }
   }
+#undef GB_AGG
+}
+
+template <int KD, bool PART>
+const void* agg_kernel_kd(int32_t vd, int g) {
+  switch (vd) {
+    case AGG_I32: return agg_row<KD, AGG_I32, PART>(g);
+    case AGG_I64: return agg_row<KD, AGG_I64, PART>(g);
+    case AGG_F32: return agg_row<KD, AGG_F32, PART>(g);
+    default: return nullptr;
+  }
+}
+
+const void* agg_kernel(int32_t kd, int32_t vd, int g, bool part) {
+  if (kd == AGG_I32) return part ? agg_kernel_kd<AGG_I32, true>(vd, g) : agg_kernel_kd<AGG_I32, false>(vd, g);
+  return part ? agg_kernel_kd<AGG_I64, true>(vd, g) : agg_kernel_kd<AGG_I64, false>(vd, g);
 }
 
 template <int KD>
-const void* agg_kernel(int32_t vd, int g) {
-  switch (vd) {
-    case AGG_I32: return agg_row<KD, AGG_I32>(g);
-    case AGG_I64: return agg_row<KD, AGG_I64>(g);
-    case AGG_F32: return agg_row<KD, AGG_F32>(g);
-    default: return nullptr;
-  }
+const void* scatter_kd(int32_t vd, bool hasv) {
+  if (!hasv) return reinterpret_cast<const void*>(&gb_scatter_kernel<KD, AGG_I32, false>);
+  if (vd == AGG_I64) return reinterpret_cast<const void*>(&gb_scatter_kernel<KD, AGG_I64, true>);
+  return reinterpret_cast<const void*>(&gb_scatter_kernel<KD, AGG_I32, true>);  // 4-byte values move as bits
+}
+
+template <int KD>
+const void* scatter_tiled_kd(int32_t vd, bool hasv) {
+  if (!hasv) return reinterpret_cast<const void*>(&gb_scatter_tiled_kernel<KD, AGG_I32, false>);
+  if (vd == AGG_I64) return reinterpret_cast<const void*>(&gb_scatter_tiled_kernel<KD, AGG_I64, true>);
+  return reinterpret_cast<const void*>(&gb_scatter_tiled_kernel<KD, AGG_I32, true>);
 }
 
 const void* init_kernel(int g) {
@@ -400,6 +728,17 @@ const void* emit_kernel(int g) {
   }
 }
 
+int launch_lds(const void* fn, int64_t grid, int block, size_t lds, Args* args, hipStream_t stream) {
+  void* kargs[] = {args};
+  const hipError_t e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(block), kargs, lds, stream);
+  if (e != hipSuccess) {
+    record_hip_error((int32_t)e);
+    (void)hipGetLastError();
+    return AGG_E_HIP;
+  }
+  return AGG_OK;
+}
+
 }  // namespace gb
 }  // namespace agg
 
@@ -413,6 +752,8 @@ struct agg_groupby_s {
   int64_t max_n = 0, max_groups = 0;
   void* ws = nullptr;
   Table t{};
+  Part pt{};           // bits == 0: the direct path
+  int agg_blocks = 1;  // aggregation workgroups resident per CU
 };
 
 extern "C" {
@@ -433,24 +774,50 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   while (cap < 2 * max_groups) cap <<= 1;
   const int64_t slots = cap + 1;
   const bool dig = g == G_SUM_F32;
+  // partitioned when an LDS table would be more than half full of groups;
+  // partitions then hold about a quarter of a table each
+  const int L = lds_slots_of(g);
+  int bits = 0;
+  if (max_groups > L / 2) {
+    while (bits < kMaxPartBits && ((int64_t)L / 4 << bits) < max_groups) ++bits;
+    if (bits == 0) bits = 1;
+  }
+  const int64_t P = bits ? (int64_t)1 << bits : 0;
+  const int64_t crow = bits ? std::max<int64_t>(1, std::min<int64_t>(max_n, kChunkRows)) : 0;
+  const int kw = width_of(key_dtype), vw = op == AGG_COUNT ? 0 : width_of(val_dtype);
   auto up = [](int64_t x) { return (x + 255) & ~(int64_t)255; };
   const int64_t b_key = up(slots * 8), b_cnt = up(slots * 8), b_val = up(slots * 8);
   const int64_t b_dig = dig ? up(slots * 8 * kDigits) : 256, b_flags = up(slots * 4), b_state = 256;
+  const int64_t b_hist = up(P * kMaxHistWg * 4), b_tot = up(P * 4 + 4), b_start = up(P * 4 + 4),
+                b_pk = up(crow * kw), b_pv = up(crow * vw);
+  const int64_t total = b_key + b_cnt + b_val + b_dig + b_flags + b_state + b_hist + b_tot + b_start +
+                        b_pk + b_pv;
   agg_groupby_s* p = new (std::nothrow) agg_groupby_s();
   if (!p) return AGG_E_NOMEM;
-  if (hipMalloc(&p->ws, (size_t)(b_key + b_cnt + b_val + b_dig + b_flags + b_state)) != hipSuccess) {
+  if (hipMalloc(&p->ws, (size_t)total) != hipSuccess) {
     (void)hipGetLastError();
     delete p;
     return AGG_E_NOMEM;
   }
-  char* base = static_cast<char*>(p->ws);
-  p->t.key = reinterpret_cast<int64_t*>(base);
-  p->t.cnt = reinterpret_cast<uint64_t*>(base + b_key);
-  p->t.val = reinterpret_cast<int64_t*>(base + b_key + b_cnt);
-  p->t.dig = reinterpret_cast<int64_t*>(base + b_key + b_cnt + b_val);
-  p->t.flags = reinterpret_cast<int32_t*>(base + b_key + b_cnt + b_val + b_dig);
-  p->t.state = reinterpret_cast<int32_t*>(base + b_key + b_cnt + b_val + b_dig + b_flags);
+  char* c = static_cast<char*>(p->ws);
+  auto take = [&c](int64_t bytes) {
+    char* r = c;
+    c += bytes;
+    return r;
+  };
+  p->t.key = reinterpret_cast<int64_t*>(take(b_key));
+  p->t.cnt = reinterpret_cast<uint64_t*>(take(b_cnt));
+  p->t.val = reinterpret_cast<int64_t*>(take(b_val));
+  p->t.dig = reinterpret_cast<int64_t*>(take(b_dig));
+  p->t.flags = reinterpret_cast<int32_t*>(take(b_flags));
+  p->t.state = reinterpret_cast<int32_t*>(take(b_state));
   p->t.cap = cap;
+  p->pt.hist = reinterpret_cast<uint32_t*>(take(b_hist));
+  p->pt.tot = reinterpret_cast<uint32_t*>(take(b_tot));
+  p->pt.start = reinterpret_cast<uint32_t*>(take(b_start));
+  p->pt.pk = take(b_pk);
+  p->pt.pv = vw ? take(b_pv) : nullptr;
+  p->pt.bits = bits;
   p->device = dev;
   p->key_dtype = key_dtype;
   p->val_dtype = val_dtype;
@@ -458,6 +825,15 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   p->gop = g;
   p->max_n = max_n;
   p->max_groups = max_groups;
+  // aggregation grids are sized to what the chip holds at once (no second, mostly idle wave of workgroups)
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, agg_kernel(key_dtype, val_dtype, g, bits != 0), kThreads, 0) !=
+          hipSuccess ||
+      nb < 1) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  p->agg_blocks = nb;
   *out = p;
   return AGG_OK;
 }
@@ -470,7 +846,7 @@ int agg_groupby_run(agg_groupby_t p, const void* keys, const void* vals, int64_t
     return AGG_E_INVALID;
   if (n > 0) {
     int rc = check_pointer(keys, n * kw, AGG_SRC_DEVICE, p->device);
-    if (rc == AGG_OK) rc = check_pointer(vals, n * vw, AGG_SRC_DEVICE, p->device);
+    if (rc == AGG_OK && p->op != AGG_COUNT) rc = check_pointer(vals, n * vw, AGG_SRC_DEVICE, p->device);
     if (rc != AGG_OK) return rc;
   }
   int rc = check_out_pointer(groups, p->max_groups * (int64_t)sizeof(agg_group), p->device);
@@ -478,8 +854,9 @@ int agg_groupby_run(agg_groupby_t p, const void* keys, const void* vals, int64_t
   if (rc != AGG_OK) return rc;
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
   const int cu = device_cu(p->device);
-  Args a;
+  Args a{};
   a.t = p->t;
+  a.pt = p->pt;
   a.keys = keys;
   a.vals = vals;
   a.n = n;
@@ -488,18 +865,49 @@ int agg_groupby_run(agg_groupby_t p, const void* keys, const void* vals, int64_t
   a.ngroups = ngroups;
   a.is_avg = p->op == AGG_AVG;
   a.op = p->op;
-  const int64_t table_grid = std::min<int64_t>(ceil_div(p->t.cap + 1, kThreads), (int64_t)cu * 8);
-  rc = launch(init_kernel(p->gop), (int)std::max<int64_t>(table_grid, 1), kThreads, &a.t, stream);
+  const int64_t table_grid = std::max<int64_t>(1, std::min<int64_t>(ceil_div(p->t.cap + 1, kThreads), (int64_t)cu * 8));
+  rc = launch(init_kernel(p->gop), (int)table_grid, kThreads, &a.t, stream);
   if (rc != AGG_OK) return rc;
-  if (n > 0) {
-    const void* fn = p->key_dtype == AGG_I32 ? agg_kernel<AGG_I32>(p->val_dtype, p->gop)
-                                             : agg_kernel<AGG_I64>(p->val_dtype, p->gop);
-    if (!fn) return AGG_E_INVALID;
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, kThreads * 16), (int64_t)cu * 4));
-    rc = launch(fn, (int)grid, kThreads, &a, stream);
+  if (n > 0 && p->pt.bits == 0) {
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, kThreads * 16), (int64_t)cu * p->agg_blocks));
+    rc = launch(agg_kernel(p->key_dtype, p->val_dtype, p->gop, false), (int)grid, kThreads, &a, stream);
     if (rc != AGG_OK) return rc;
+  } else if (n > 0) {
+    const int64_t P = (int64_t)1 << p->pt.bits;
+    const size_t lds = (size_t)P * 4;
+    const bool hasv = p->op != AGG_COUNT;
+    const void* hist = p->key_dtype == AGG_I32 ? reinterpret_cast<const void*>(&gb_hist_kernel<AGG_I32>)
+                                               : reinterpret_cast<const void*>(&gb_hist_kernel<AGG_I64>);
+    const bool tiled = p->pt.bits <= kTileMaxBits;
+    const void* scat = tiled ? (p->key_dtype == AGG_I32 ? scatter_tiled_kd<AGG_I32>(p->val_dtype, hasv)
+                                                        : scatter_tiled_kd<AGG_I64>(p->val_dtype, hasv))
+                             : (p->key_dtype == AGG_I32 ? scatter_kd<AGG_I32>(p->val_dtype, hasv)
+                                                        : scatter_kd<AGG_I64>(p->val_dtype, hasv));
+    const void* aggk = agg_kernel(p->key_dtype, p->val_dtype, p->gop, true);
+    for (int64_t c0 = 0; c0 < n; c0 += kChunkRows) {
+      const int64_t m = std::min<int64_t>(kChunkRows, n - c0);
+      a.keys = static_cast<const char*>(keys) + c0 * kw;
+      a.vals = static_cast<const char*>(vals) + c0 * vw;
+      a.n = m;
+      a.pt.g1 = (int)std::min<int64_t>(kMaxHistWg, ceil_div(m, kHistRows));
+      a.pt.rows_per_wg = ceil_div(m, a.pt.g1);
+      if ((rc = launch_lds(hist, a.pt.g1, kThreads, lds, &a, stream)) != AGG_OK) return rc;
+      if ((rc = launch_lds(reinterpret_cast<const void*>(&gb_scan_rows_kernel), ceil_div(P, kThreads / 64), kThreads,
+                           0, &a, stream)) != AGG_OK)
+        return rc;
+      if ((rc = launch_lds(reinterpret_cast<const void*>(&gb_scan_tot_kernel), 1, kScanThreads, 0, &a, stream)) !=
+          AGG_OK)
+        return rc;
+      if ((rc = launch_lds(scat, a.pt.g1, tiled ? kTileThreads : kThreads, tiled ? 0 : lds, &a, stream)) != AGG_OK)
+        return rc;
+      const int64_t agrid = std::max<int64_t>(1, std::min<int64_t>(ceil_div(m, kThreads * 8), (int64_t)cu * p->agg_blocks));
+      if ((rc = launch_lds(aggk, agrid, kThreads, 0, &a, stream)) != AGG_OK) return rc;
+    }
+    a.keys = keys;
+    a.vals = vals;
+    a.n = n;
   }
-  rc = launch(emit_kernel(p->gop), (int)std::max<int64_t>(table_grid, 1), kThreads, &a, stream);
+  rc = launch(emit_kernel(p->gop), (int)table_grid, kThreads, &a, stream);
   if (rc != AGG_OK) return rc;
   return launch(reinterpret_cast<const void*>(&gb_finish_kernel), 1, 64, &a, stream);
 }

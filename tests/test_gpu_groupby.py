@@ -183,3 +183,34 @@ def test_groupby_errors(agg):
         g.run(k, k, n=200)                                                    # beyond max_n
     with pytest.raises(agg.AggError):
         g.run(np.zeros(10, np.int32).ctypes.data, k, n=10)                    # pageable host keys
+
+
+def test_groupby_partitioned_with_few_actual_groups(agg):
+    """A plan sized for many groups (partitioned path) on an input with few."""
+    n = 500_009
+    keys = make_keys(n, "i64", 37, seed=31)
+    for vdt in DTS:
+        vals = make_vals(n, vdt, seed=32)
+        for op in ("sum", "min", "count"):
+            run_case(agg, keys, vals, op, max_groups=100_000, ctx=f"few groups, big plan {vdt} {op}")
+
+
+def test_groupby_multi_chunk_closed_form(agg):
+    """More rows than one partitioning chunk (2^26): per-key sums with closed forms."""
+    import torch
+    n = (1 << 26) + 4099
+    card = 3001
+    idx = torch.arange(n, dtype=torch.int64, device="cuda")
+    keys = (idx % card).to(torch.int32)
+    cnt = np.bincount(np.arange(n, dtype=np.int64) % card, minlength=card)
+    got = agg.GroupBy("i32", "i64", "sum", max_n=n, max_groups=card).run(keys, idx)
+    r = np.arange(card, dtype=np.int64)
+    want_sum = r * cnt + card * cnt * (cnt - 1) // 2          # sum of r + card*j for j < cnt[r]
+    assert [g[0] for g in got] == list(range(card))
+    assert [g[3] for g in got] == cnt.tolist()
+    assert [g[1] for g in got] == want_sum.tolist()
+    vf = ((idx % 7) - 3).to(torch.float32)
+    got = agg.GroupBy("i32", "f32", "sum", max_n=n, max_groups=card).run(keys, vf)
+    i = np.arange(n, dtype=np.int64)
+    want_f = np.bincount(i % card, weights=((i % 7) - 3).astype(np.float64), minlength=card)
+    assert [g[2] for g in got] == want_f.tolist()
