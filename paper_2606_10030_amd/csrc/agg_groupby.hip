@@ -45,19 +45,29 @@ constexpr int kThreads = 256;
 constexpr int kLdsProbes = 16;
 constexpr int kAggRows = 8;           // rows whose loads a thread keeps in flight
 constexpr int kMaxPartBits = 14;      // at most 16384 partitions
+constexpr int kMinPartBits = 5;       // at least 32
 constexpr int64_t kChunkRows = (int64_t)1 << 26;
 constexpr int64_t kHistRows = (int64_t)1 << 16;    // rows per histogram / scatter workgroup
 constexpr int kMaxHistWg = (int)(kChunkRows / kHistRows);
 constexpr int kScanThreads = 1024;
 constexpr int kTileThreads = 1024;    // tiled scatter: rows staged in LDS per tile
-constexpr int kTileRows = 8192;
-constexpr int kTileMaxBits = 9;       // tiled scatter for up to 512 partitions
+constexpr int kTileMaxBits = 11;      // tiled scatter for up to 2048 partitions
+// rows per tile: 8192, or 4096 where 8-byte keys and values would not fit LDS
+template <int KD, int VD, bool HASV>
+constexpr int tile_rows() { return (KD == AGG_I64 && VD == AGG_I64 && HASV) ? 4096 : 8192; }
 
 enum GOp { G_COUNT = 0, G_SUM_INT, G_MIN_INT, G_MAX_INT, G_SUM_F32, G_MIN_F32, G_MAX_F32 };
 
+// LDS table slots: direct path (256 threads, three workgroups per CU) and
+// partitioned path (1024 threads, one workgroup per CU with a table twice
+// as large, so that a partition can hold twice as many keys).
 template <int G>
 constexpr int lds_slots() { return G == G_SUM_F32 ? 512 : 2048; }
 inline int lds_slots_of(int g) { return g == G_SUM_F32 ? 512 : 2048; }
+template <int G>
+constexpr int part_slots() { return G == G_SUM_F32 ? 1024 : 4096; }
+inline int part_slots_of(int g) { return g == G_SUM_F32 ? 1024 : 4096; }
+constexpr int kPartThreads = 1024;
 
 struct Table {
   int64_t* key;        // cap + 1 slots; slot cap holds the key INT64_MIN
@@ -107,6 +117,8 @@ __device__ __forceinline__ uint64_t mix64(uint64_t k) {  // MurmurHash3's 64-bit
   k ^= k >> 33;
   return k;
 }
+
+__device__ __forceinline__ int64_t ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Partition of a key: the top bits of its hash (table slots use the low bits).
 __device__ __forceinline__ uint32_t part_of(int64_t k, int bits) {
@@ -309,18 +321,19 @@ __global__ void __launch_bounds__(kThreads) gb_scatter_kernel(Args a) {
   }
 }
 
-// Scatter through LDS: each tile of kTileRows rows is counting-sorted by
+// Scatter through LDS: each tile of rows is counting-sorted by
 // partition in LDS first, so the rows of one partition leave as one
 // contiguous run (coalesced stores) instead of one scattered store per row.
 template <int KD, int VD, bool HASV>
 __global__ void __launch_bounds__(kTileThreads) gb_scatter_tiled_kernel(Args a) {
   using KT = typename std::conditional<KD == AGG_I32, int32_t, int64_t>::type;
   using VT = typename std::conditional<VD == AGG_I64, int64_t, uint32_t>::type;
-  constexpr int R = kTileRows / kTileThreads;
+  constexpr int TR = tile_rows<KD, VD, HASV>();
+  constexpr int R = TR / kTileThreads;
   constexpr int PM = 1 << kTileMaxBits;
-  __shared__ KT skey[kTileRows];
-  __shared__ VT sval[HASV ? kTileRows : 1];
-  __shared__ uint16_t spart[kTileRows];
+  __shared__ KT skey[TR];
+  __shared__ VT sval[HASV ? TR : 1];
+  __shared__ uint16_t spart[TR];
   __shared__ uint32_t tcnt[PM], toff[PM], cur[PM];
   const int P = 1 << a.pt.bits;
   const int tid = threadIdx.x;
@@ -331,8 +344,8 @@ __global__ void __launch_bounds__(kTileThreads) gb_scatter_tiled_kernel(Args a) 
   __syncthreads();
   const int64_t lo = (int64_t)blockIdx.x * a.pt.rows_per_wg;
   const int64_t hi = std::min<int64_t>(lo + a.pt.rows_per_wg, a.n);
-  for (int64_t t0 = lo; t0 < hi; t0 += kTileRows) {
-    const int rows = (int)std::min<int64_t>(kTileRows, hi - t0);
+  for (int64_t t0 = lo; t0 < hi; t0 += TR) {
+    const int rows = (int)std::min<int64_t>(TR, hi - t0);
     KT k[R];
     VT v[R];
     uint32_t pp[R], rank[R];
@@ -395,9 +408,9 @@ __global__ void __launch_bounds__(kTileThreads) gb_scatter_tiled_kernel(Args a) 
 
 // ---- aggregation into LDS tables, flushed into the global table ----
 
-template <int G>
+template <int G, int L_, int NT>
 struct LdsTable {
-  static constexpr int L = lds_slots<G>();
+  static constexpr int L = L_;
   static constexpr bool kDig = G == G_SUM_F32;
   int64_t key[L];
   uint64_t cnt[L];
@@ -406,7 +419,7 @@ struct LdsTable {
   int32_t flags[kDig ? L : 1];
 
   __device__ void clear() {
-    for (int e = threadIdx.x; e < L; e += kThreads) {
+    for (int e = threadIdx.x; e < L; e += NT) {
       key[e] = kEmpty;
       cnt[e] = 0;
       if constexpr (!kDig) val[e] = val_identity<G>();
@@ -469,7 +482,7 @@ struct LdsTable {
   }
 
   __device__ void flush(const Table& t) {
-    for (int e = threadIdx.x; e < L; e += kThreads) {
+    for (int e = threadIdx.x; e < L; e += NT) {
       const int64_t k = key[e];
       if (k == kEmpty) continue;
       const int64_t g = global_slot(t, k);
@@ -492,7 +505,7 @@ struct LdsTable {
 // Direct path: every workgroup sweeps the rows grid-stride into one LDS table.
 template <int KD, int VD, int G>
 __global__ void __launch_bounds__(kThreads) gb_aggregate_kernel(Args a) {
-  __shared__ LdsTable<G> tab;
+  __shared__ LdsTable<G, lds_slots<G>(), kThreads> tab;
   tab.clear();
   __syncthreads();
   tab.template fold_rows<KD, VD>(a.t, a.keys, a.vals, (int64_t)blockIdx.x * kThreads + threadIdx.x, a.n,
@@ -507,8 +520,8 @@ __global__ void __launch_bounds__(kThreads) gb_aggregate_kernel(Args a) {
 // keys are all different).  Equal shares keep every workgroup equally busy
 // whatever the partition sizes.
 template <int KD, int VD, int G>
-__global__ void __launch_bounds__(kThreads) gb_aggregate_part_kernel(Args a) {
-  __shared__ LdsTable<G> tab;
+__global__ void __launch_bounds__(kPartThreads) gb_aggregate_part_kernel(Args a) {
+  __shared__ LdsTable<G, part_slots<G>(), kPartThreads> tab;
   const int P = 1 << a.pt.bits;
   int64_t r = a.n * (int64_t)blockIdx.x / gridDim.x;
   const int64_t r1 = a.n * ((int64_t)blockIdx.x + 1) / gridDim.x;
@@ -525,7 +538,7 @@ __global__ void __launch_bounds__(kThreads) gb_aggregate_part_kernel(Args a) {
     const int64_t seg_end = std::min<int64_t>(r1, (int64_t)a.pt.start[p + 1]);
     tab.clear();
     __syncthreads();
-    tab.template fold_rows<KD, VD>(a.t, a.pt.pk, a.pt.pv, r + threadIdx.x, seg_end, kThreads);
+    tab.template fold_rows<KD, VD>(a.t, a.pt.pk, a.pt.pv, r + threadIdx.x, seg_end, kPartThreads);
     __syncthreads();
     tab.flush(a.t);
     __syncthreads();
@@ -600,10 +613,19 @@ __global__ void __launch_bounds__(kThreads) gb_emit_kernel(Args a) {
   const Table& t = a.t;
   unsigned long long* emitted = reinterpret_cast<unsigned long long*>(t.state + 2);
   const int64_t stride = (int64_t)gridDim.x * kThreads;
-  for (int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x; s <= t.cap; s += stride) {
-    const bool used = s < t.cap ? t.key[s] != kEmpty : t.state[0] != 0;
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;  // lanes under this one
+  // every lane of a wave runs the same iterations (the bound is rounded up to whole waves)
+  const int64_t end = ceil_div_dev(t.cap + 1, 64) * 64;
+  for (int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x; s < end; s += stride) {
+    const bool used = s < t.cap ? t.key[s] != kEmpty : (s == t.cap && t.state[0] != 0);
+    // one counter update per wave: the wave's used slots take consecutive output indices
+    const uint64_t mask = __ballot(used);
+    unsigned long long base = 0;
+    if (lane == 0 && mask) base = atomicAdd(emitted, (unsigned long long)__popcll(mask));
+    base = __shfl(base, 0, 64);
     if (!used) continue;
-    const unsigned long long idx = atomicAdd(emitted, 1ull);
+    const unsigned long long idx = base + (unsigned long long)__popcll(mask & below);
     if ((int64_t)idx >= a.max_groups) continue;
     agg_group g;
     g.key = t.key[s];
@@ -774,13 +796,13 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   while (cap < 2 * max_groups) cap <<= 1;
   const int64_t slots = cap + 1;
   const bool dig = g == G_SUM_F32;
-  // partitioned when an LDS table would be more than half full of groups;
-  // partitions then hold about a quarter of a table each
-  const int L = lds_slots_of(g);
+  // partitioned when a direct-path LDS table would be more than half full
+  // of groups; a partition then holds at most half of its (larger) table
   int bits = 0;
-  if (max_groups > L / 2) {
-    while (bits < kMaxPartBits && ((int64_t)L / 4 << bits) < max_groups) ++bits;
-    if (bits == 0) bits = 1;
+  if (max_groups > lds_slots_of(g) / 2) {
+    const int64_t per_part = part_slots_of(g) / 2;
+    while (bits < kMaxPartBits && (per_part << bits) < max_groups) ++bits;
+    bits = std::max(bits, kMinPartBits);  // few partitions would serialise the counting atomics
   }
   const int64_t P = bits ? (int64_t)1 << bits : 0;
   const int64_t crow = bits ? std::max<int64_t>(1, std::min<int64_t>(max_n, kChunkRows)) : 0;
@@ -827,7 +849,8 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   p->max_groups = max_groups;
   // aggregation grids are sized to what the chip holds at once (no second, mostly idle wave of workgroups)
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, agg_kernel(key_dtype, val_dtype, g, bits != 0), kThreads, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, agg_kernel(key_dtype, val_dtype, g, bits != 0),
+                                                   bits ? kPartThreads : kThreads, 0) !=
           hipSuccess ||
       nb < 1) {
     (void)hipGetLastError();
@@ -900,8 +923,9 @@ int agg_groupby_run(agg_groupby_t p, const void* keys, const void* vals, int64_t
         return rc;
       if ((rc = launch_lds(scat, a.pt.g1, tiled ? kTileThreads : kThreads, tiled ? 0 : lds, &a, stream)) != AGG_OK)
         return rc;
-      const int64_t agrid = std::max<int64_t>(1, std::min<int64_t>(ceil_div(m, kThreads * 8), (int64_t)cu * p->agg_blocks));
-      if ((rc = launch_lds(aggk, agrid, kThreads, 0, &a, stream)) != AGG_OK) return rc;
+      const int64_t agrid =
+          std::max<int64_t>(1, std::min<int64_t>(ceil_div(m, kPartThreads * 8), (int64_t)cu * p->agg_blocks));
+      if ((rc = launch_lds(aggk, agrid, kPartThreads, 0, &a, stream)) != AGG_OK) return rc;
     }
     a.keys = keys;
     a.vals = vals;

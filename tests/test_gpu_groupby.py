@@ -193,6 +193,10 @@ def test_groupby_partitioned_with_few_actual_groups(agg):
         vals = make_vals(n, vdt, seed=32)
         for op in ("sum", "min", "count"):
             run_case(agg, keys, vals, op, max_groups=100_000, ctx=f"few groups, big plan {vdt} {op}")
+    # more partitions than the tiled scatter takes: the row-by-row scatter
+    many = make_keys(n, "i32", 20_000, seed=33)
+    for vdt in ("f32", "i64"):
+        run_case(agg, many, make_vals(n, vdt, seed=34), "sum", max_groups=6_000_000, ctx=f"row scatter {vdt}")
 
 
 def test_groupby_multi_chunk_closed_form(agg):
