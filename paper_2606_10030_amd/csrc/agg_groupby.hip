@@ -161,10 +161,10 @@ __device__ __forceinline__ int64_t load_ival(const void* p, int64_t i) {
 }
 
 // Fold one row into a slot (LDS or global: the pointers decide).
-template <int G>
-__device__ __forceinline__ void apply(uint64_t* cnt, int64_t* val, int64_t* dig, int32_t* flags, int64_t iv,
-                                      float fv) {
-  atomicAdd(reinterpret_cast<unsigned long long*>(cnt), 1ull);
+template <int G, typename CT>
+__device__ __forceinline__ void apply(CT* cnt, int64_t* val, int64_t* dig, int32_t* flags, int64_t iv, float fv) {
+  if constexpr (sizeof(CT) == 8) atomicAdd(reinterpret_cast<unsigned long long*>(cnt), 1ull);
+  else atomicAdd(reinterpret_cast<unsigned int*>(cnt), 1u);
   if constexpr (G == G_SUM_INT) atomicAdd(reinterpret_cast<unsigned long long*>(val), (unsigned long long)iv);
   if constexpr (G == G_MIN_INT) atomicMin(reinterpret_cast<long long*>(val), (long long)iv);
   if constexpr (G == G_MAX_INT) atomicMax(reinterpret_cast<long long*>(val), (long long)iv);
@@ -213,6 +213,14 @@ __device__ __forceinline__ void apply_global(const Table& t, int64_t s, int64_t 
   apply<G>(t.cnt + s, t.val + s, t.dig + (G == G_SUM_F32 ? s * kDigits : 0), t.flags + s, iv, fv);
 }
 
+// A row whose key found no LDS slot: straight into the global table.  Rare,
+// so kept out of line to keep the hot loop small.
+template <int G>
+__device__ __attribute__((noinline)) void spill_row(Table t, int64_t k, int64_t iv, float fv) {
+  const int64_t g = global_slot(t, k);
+  if (g >= 0) apply_global<G>(t, g, iv, fv);
+}
+
 // ---- histogram / prefix sums / scatter of the partitioned path ----
 
 template <int KD>
@@ -226,10 +234,7 @@ __global__ void __launch_bounds__(kThreads) gb_hist_kernel(Args a) {
   for (int64_t base = lo + threadIdx.x; base < hi; base += kThreads * kAggRows) {
     int64_t kk[kAggRows];
 #pragma unroll
-    for (int r = 0; r < kAggRows; ++r) {
-      const int64_t i = base + (int64_t)r * kThreads;
-      kk[r] = i < hi ? load_key<KD>(a.keys, i) : 0;
-    }
+    for (int r = 0; r < kAggRows; ++r) kk[r] = load_key<KD>(a.keys, std::min<int64_t>(base + (int64_t)r * kThreads, hi - 1));
 #pragma unroll
     for (int r = 0; r < kAggRows; ++r)
       if (base + (int64_t)r * kThreads < hi) atomicAdd(&h[part_of(kk[r], a.pt.bits)], 1u);
@@ -350,11 +355,14 @@ __global__ void __launch_bounds__(kTileThreads) gb_scatter_tiled_kernel(Args a) 
     VT v[R];
     uint32_t pp[R], rank[R];
 #pragma unroll
+    for (int r = 0; r < R; ++r) {  // all loads first (rows past the tile re-load its last row)
+      const int j = std::min(r * kTileThreads + tid, rows - 1);
+      k[r] = static_cast<const KT*>(a.keys)[t0 + j];
+      if constexpr (HASV) v[r] = static_cast<const VT*>(a.vals)[t0 + j];
+    }
+#pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int j = r * kTileThreads + tid;
-      if (j < rows) {
-        k[r] = static_cast<const KT*>(a.keys)[t0 + j];
-        if constexpr (HASV) v[r] = static_cast<const VT*>(a.vals)[t0 + j];
+      if (r * kTileThreads + tid < rows) {
         pp[r] = part_of((int64_t)k[r], a.pt.bits);
         rank[r] = atomicAdd(&tcnt[pp[r]], 1u);
       }
@@ -413,7 +421,7 @@ struct LdsTable {
   static constexpr int L = L_;
   static constexpr bool kDig = G == G_SUM_F32;
   int64_t key[L];
-  uint64_t cnt[L];
+  uint32_t cnt[L];     // rows per table stay below 2^32 (a workgroup's share is at most 2^28 rows)
   int64_t val[kDig ? 1 : L];
   int64_t dig[kDig ? L * kDigits : 1];
   int32_t flags[kDig ? L : 1];
@@ -441,16 +449,15 @@ struct LdsTable {
       float fvv[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int64_t i = base + r * step;
-        kk[r] = kEmpty;
+        // rows past the end re-load the last row (in bounds, never folded): no
+        // branch around the loads, so all of them issue before the first wait
+        const int64_t i = std::min<int64_t>(base + r * step, last - 1);
+        kk[r] = load_key<KD>(keys, i);
         ivv[r] = 0;
         fvv[r] = 0.0f;
-        if (i < last) {
-          kk[r] = load_key<KD>(keys, i);
-          if constexpr (G != G_COUNT) {
-            if constexpr (VD == AGG_F32) fvv[r] = static_cast<const float*>(vals)[i];
-            else ivv[r] = load_ival<VD>(vals, i);
-          }
+        if constexpr (G != G_COUNT) {
+          if constexpr (VD == AGG_F32) fvv[r] = static_cast<const float*>(vals)[i];
+          else ivv[r] = load_ival<VD>(vals, i);
         }
       }
 #pragma unroll
@@ -474,8 +481,7 @@ struct LdsTable {
           apply<G>(&cnt[s], kDig ? nullptr : &val[s], kDig ? &dig[s * kDigits] : nullptr,
                    kDig ? &flags[s] : nullptr, ivv[r], fvv[r]);
         } else {
-          const int64_t g = global_slot(t, k);
-          if (g >= 0) apply_global<G>(t, g, ivv[r], fvv[r]);
+          { const int64_t g = global_slot(t, k); if (g >= 0) apply_global<G>(t, g, ivv[r], fvv[r]); }
         }
       }
     }
@@ -560,13 +566,16 @@ __global__ void __launch_bounds__(kThreads) gb_init_kernel(Table t) {
   if (blockIdx.x == 0 && threadIdx.x < 4) t.state[threadIdx.x] = 0;
 }
 
-// The fixed-point digits of an exact sum, rounded once to double (ties to even).
+// The fixed-point digits of an exact sum, rounded once to double (ties to
+// even).  Only static indexing, so the digits stay in registers.
 __device__ double digits_to_double(const int64_t* src, int32_t flags) {
   if ((flags & 1) || ((flags & 2) && (flags & 4))) return __builtin_nan("");
   if (flags & 2) return __builtin_inf();
   if (flags & 4) return -__builtin_inf();
   int64_t d[kNormDigits];
+#pragma unroll
   for (int k = 0; k < kNormDigits; ++k) d[k] = k < kDigits ? src[k] : 0;
+#pragma unroll
   for (int k = 0; k < kNormDigits - 1; ++k) {  // carries: digits 0..9 into [0, 2^32)
     const int64_t c = d[k] >> 32;
     d[k] -= c * 4294967296ll;
@@ -574,59 +583,97 @@ __device__ double digits_to_double(const int64_t* src, int32_t flags) {
   }
   const bool neg = d[kNormDigits - 1] < 0;
   if (neg) {
+#pragma unroll
     for (int k = 0; k < kNormDigits; ++k) d[k] = -d[k];
+#pragma unroll
     for (int k = 0; k < kNormDigits - 1; ++k) {
       const int64_t c = d[k] >> 32;
       d[k] -= c * 4294967296ll;
       d[k + 1] += c;
     }
   }
-  auto bit = [&](int b) -> uint64_t { return (uint64_t)(d[b >> 5] >> (b & 31)) & 1u; };
-  int top = -1;
-  for (int b = 32 * kNormDigits - 1; b >= 0; --b)
-    if (bit(b)) { top = b; break; }
-  if (top < 0) return 0.0;
-  uint64_t mant = 0;
-  int e = 0;
-  if (top <= 52) {
-    for (int b = top; b >= 0; --b) mant = (mant << 1) | bit(b);
+  // |sum| < 2^308 * 2^-149, so the top digit is zero and all are in [0, 2^32)
+  int t = -1;  // highest nonzero digit
+#pragma unroll
+  for (int k = 0; k < kNormDigits; ++k)
+    if (d[k] != 0) t = k;
+  if (t < 0) return 0.0;
+  // V = w2:w1:w0, digits t, t-1, t-2 (zero below digit 0); lower digits only
+  // decide the sticky bit
+  uint64_t w2 = 0, w1 = 0, w0 = 0;
+  bool sticky = false;
+#pragma unroll
+  for (int k = 0; k < kNormDigits; ++k) {
+    const uint64_t v = (uint64_t)d[k];
+    if (k == t) w2 = v;
+    if (k == t - 1) w1 = v;
+    if (k == t - 2) w0 = v;
+    if (k < t - 2) sticky |= v != 0;
+  }
+  const int p = 95 - __builtin_clz((uint32_t)w2);  // highest set bit of V, 64..95
+  const int sh = p - 52;                            // low bits rounded away, 12..43
+  const uint64_t hi = (w2 << 32) | w1;              // V = hi * 2^32 + w0
+  uint64_t mant, rnd;
+  if (sh <= 32) {
+    mant = (hi << (32 - sh)) | (w0 >> sh);
+    rnd = (w0 >> (sh - 1)) & 1u;
+    sticky |= (w0 & ((1ull << (sh - 1)) - 1)) != 0;
   } else {
-    for (int b = top; b >= top - 52; --b) mant = (mant << 1) | bit(b);
-    e = top - 52;
-    const uint64_t rnd = bit(top - 53);
-    bool sticky = false;
-    for (int b = top - 54; b >= 0 && !sticky; --b) sticky = bit(b);
-    if (rnd && (sticky || (mant & 1))) {
-      ++mant;
-      if (mant == (1ull << 53)) {
-        mant >>= 1;
-        ++e;
-      }
+    const int r = sh - 33;  // the rounding bit's index in hi
+    mant = hi >> (sh - 32);
+    rnd = (hi >> r) & 1u;
+    sticky |= (hi & ((1ull << r) - 1)) != 0 || w0 != 0;
+  }
+  int e = sh + 32 * (t - 2) - 149;
+  if (rnd && (sticky || (mant & 1))) {
+    ++mant;
+    if (mant == (1ull << 53)) {
+      mant >>= 1;
+      ++e;
     }
   }
-  const double r = __builtin_ldexp((double)mant, e - 149);
+  const double r = __builtin_ldexp((double)mant, e);
   return neg ? -r : r;
 }
 
+// Workgroup w writes the used slots of its contiguous slot range: it counts
+// them, takes one output range with a single atomic, and each thread writes
+// its slots at its prefix within that range (one counter update per
+// workgroup: updates of one address serialise).
 template <int G>
 __global__ void __launch_bounds__(kThreads) gb_emit_kernel(Args a) {
+  __shared__ uint32_t wsum[kThreads / 64];
+  __shared__ unsigned long long base_sh;
   const Table& t = a.t;
-  unsigned long long* emitted = reinterpret_cast<unsigned long long*>(t.state + 2);
-  const int64_t stride = (int64_t)gridDim.x * kThreads;
-  const int lane = threadIdx.x & 63;
-  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;  // lanes under this one
-  // every lane of a wave runs the same iterations (the bound is rounded up to whole waves)
-  const int64_t end = ceil_div_dev(t.cap + 1, 64) * 64;
-  for (int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x; s < end; s += stride) {
-    const bool used = s < t.cap ? t.key[s] != kEmpty : (s == t.cap && t.state[0] != 0);
-    // one counter update per wave: the wave's used slots take consecutive output indices
-    const uint64_t mask = __ballot(used);
-    unsigned long long base = 0;
-    if (lane == 0 && mask) base = atomicAdd(emitted, (unsigned long long)__popcll(mask));
-    base = __shfl(base, 0, 64);
-    if (!used) continue;
-    const unsigned long long idx = base + (unsigned long long)__popcll(mask & below);
-    if ((int64_t)idx >= a.max_groups) continue;
+  const int64_t slots = t.cap + 1;
+  const int64_t per = ceil_div_dev(slots, gridDim.x);
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = std::min<int64_t>(lo + per, slots);
+  auto used = [&](int64_t s) { return s < t.cap ? t.key[s] != kEmpty : t.state[0] != 0; };
+  uint32_t mine = 0;
+  for (int64_t s = lo + threadIdx.x; s < hi; s += kThreads) mine += used(s) ? 1u : 0u;
+  // exclusive prefix of the per-thread counts over the workgroup
+  const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
+  uint32_t incl = mine;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t before = incl - mine, total = 0;
+  for (int v = 0; v < kThreads / 64; ++v) {
+    if (v < w) before += wsum[v];
+    total += wsum[v];
+  }
+  if (threadIdx.x == 0)
+    base_sh = total ? atomicAdd(reinterpret_cast<unsigned long long*>(t.state + 2), (unsigned long long)total) : 0;
+  __syncthreads();
+  unsigned long long idx = base_sh + before;
+  for (int64_t s = lo + threadIdx.x; s < hi; s += kThreads) {
+    if (!used(s)) continue;
+    const unsigned long long my = idx++;
+    if ((int64_t)my >= a.max_groups) continue;
     agg_group g;
     g.key = t.key[s];
     g.count = (int64_t)t.cnt[s];
@@ -648,7 +695,7 @@ __global__ void __launch_bounds__(kThreads) gb_emit_kernel(Args a) {
       const int64_t v = t.val[s];
       g.f64 = v == val_identity<G>() ? (double)__builtin_nanf("") : (double)f32_unorder((int32_t)v);
     }
-    a.out[idx] = g;
+    a.out[my] = g;
   }
 }
 
@@ -788,7 +835,7 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   if ((key_dtype != AGG_I32 && key_dtype != AGG_I64) || width_of(val_dtype) == 0 || g < 0) return AGG_E_INVALID;
   if (max_n < 0 || max_groups < 1 || max_groups > ((int64_t)1 << 32)) return AGG_E_INVALID;
   if (g == G_SUM_F32 && max_n > ((int64_t)1 << 31)) return AGG_E_INVALID;  // digit headroom
-  if (max_n > ((int64_t)1 << 40)) return AGG_E_INVALID;
+  if (max_n > ((int64_t)1 << 36)) return AGG_E_INVALID;
   int dev = 0;
   const int dr = current_device(&dev);
   if (dr != AGG_OK) return dr;

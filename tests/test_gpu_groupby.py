@@ -218,3 +218,20 @@ def test_groupby_multi_chunk_closed_form(agg):
     i = np.arange(n, dtype=np.int64)
     want_f = np.bincount(i % card, weights=((i % 7) - 3).astype(np.float64), minlength=card)
     assert [g[2] for g in got] == want_f.tolist()
+
+
+def test_groupby_float_sum_rounding_cases(agg):
+    """Group sums that land exactly between two doubles (ties to even), just
+    above a tie (sticky bit), and ones that need every digit."""
+    import torch
+    t = np.float32(2.0**53)
+    groups = {0: [t, 1.0], 1: [t, 3.0], 2: [t, 1.0, 2.0**-20], 3: [t, -1.0], 4: [2.0**-149] * 3,
+              5: [3.4e38, 3.4e38, -3.4e38, 1e-45], 6: [1.0, 2.0**-24, 2.0**-24], 7: [-t, -1.0]}
+    want = {0: 2.0**53, 1: 2.0**53 + 4, 2: 2.0**53 + 2, 3: 2.0**53 - 1, 4: 3 * 2.0**-149,
+            5: float(np.float32(3.4e38)) + 2.0**-149, 6: 1.0 + 2.0**-23, 7: -2.0**53}
+    keys = np.concatenate([np.full(len(v), k, np.int32) for k, v in groups.items()])
+    vals = np.concatenate([np.array(v, np.float32) for v in groups.values()])
+    g = agg.GroupBy("i32", "f32", "sum", max_n=keys.size, max_groups=8)
+    got = g.run(torch.from_numpy(keys).to("cuda"), torch.from_numpy(vals).to("cuda"))
+    assert [x[2] for x in got] == [want[k] for k in sorted(want)]
+    compare(got, oracle.groupby(keys, vals, "sum"), "rounding cases")
