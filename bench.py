@@ -94,6 +94,34 @@ def counters_mode(n: int):
     log("counters mode done")
 
 
+def groupby_profile_mode(cards):
+    """Dispatches for a kernel trace of group-by: 2^28 rows of int32 keys with
+    each given number of distinct values, then 3 runs each of SUM(int64),
+    SUM(float32) and COUNT; no JSON line."""
+    import torch
+    import datagen
+    import paper_2606_10030_amd as agg
+    n = 1 << 28
+    dev = {}
+    for dt in DTYPES:
+        tdt = {"i32": torch.int32, "i64": torch.int64, "f32": torch.float32}[dt]
+        h = torch.empty(n, dtype=tdt, pin_memory=True)
+        datagen.fill_ptr(h.data_ptr(), n, dt, "uniform", SEEDS[dt])
+        dev[dt] = h.to("cuda")
+    for card in cards:
+        keys = torch.remainder(dev["i32"].to(torch.int64) * 2654435761, card).to(torch.int32)
+        for vdt, op in (("i64", "sum"), ("f32", "sum"), ("i32", "count")):
+            g = agg.GroupBy("i32", vdt, op, max_n=n, max_groups=card)
+            groups = torch.empty(card * agg.GROUP_BYTES, dtype=torch.uint8, device="cuda")
+            ng = torch.zeros(1, dtype=torch.int64, device="cuda")
+            for _ in range(3):
+                g.enqueue(keys, dev[vdt], groups, ng)
+            torch.cuda.synchronize()
+            log(f"group-by {op}({vdt}) by {card} keys: {int(ng.item())} groups")
+            g.close()
+    log("group-by profile mode done")
+
+
 def bench_energy(agg, torch, dev_i32, host_i32, stream):
     """Joules per aggregation from the GPU's energy accumulator (amdsmi), for
     the on-device SUM of a 2^30-item int32 column and the same SUM end to end
@@ -310,6 +338,9 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="profiling mode for rocprofv3 --pmc: a 1 GiB device copy (calibration) "
                          "then 3 launches of each int32/int64/float32 SUM scan; no JSON line")
+    ap.add_argument("--profile-groupby", type=int, nargs="+", metavar="GROUPS",
+                    help="profiling mode for a rocprofv3 kernel trace: group-by over 2^28 rows with "
+                         "the given key counts; no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -327,6 +358,9 @@ def main():
 
     if args.counters:
         counters_mode(n)
+        return
+    if args.profile_groupby:
+        groupby_profile_mode(args.profile_groupby)
         return
 
     # ---- inputs: generated into pinned host memory, copied to HBM

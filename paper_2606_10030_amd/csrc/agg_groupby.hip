@@ -11,8 +11,8 @@
 // per (workgroup, key) instead of one per row.
 //
 // Two paths, chosen from the plan's max_groups:
-//  * direct: every workgroup's LDS table can hold all the groups; workgroups
-//    stride over the rows.
+//  * direct: every workgroup's LDS table holds all the groups at a quarter of
+//    its slots; workgroups stride over the rows.
 //  * partitioned (more groups than an LDS table holds): rows are processed in
 //    chunks; each chunk is radix-partitioned on the top bits of the key's
 //    hash (histogram, prefix sums, scatter into a staging copy), so that one
@@ -58,15 +58,14 @@ constexpr int tile_rows() { return (KD == AGG_I64 && VD == AGG_I64 && HASV) ? 40
 
 enum GOp { G_COUNT = 0, G_SUM_INT, G_MIN_INT, G_MAX_INT, G_SUM_F32, G_MIN_F32, G_MAX_F32 };
 
-// LDS table slots: direct path (256 threads, three workgroups per CU) and
-// partitioned path (1024 threads, one workgroup per CU with a table twice
-// as large, so that a partition can hold twice as many keys).
+// LDS tables: one 1024-thread workgroup per CU with a table of 4096 slots
+// (1024 for float sums, whose slots carry the digits), on both paths.
+// Measured against three 256-thread workgroups per CU with half the slots:
+// fewer, larger tables hold 2x the groups at the same load and fold faster.
+constexpr int kDirectThreads = 1024;
 template <int G>
-constexpr int lds_slots() { return G == G_SUM_F32 ? 512 : 2048; }
-inline int lds_slots_of(int g) { return g == G_SUM_F32 ? 512 : 2048; }
-template <int G>
-constexpr int part_slots() { return G == G_SUM_F32 ? 1024 : 4096; }
-inline int part_slots_of(int g) { return g == G_SUM_F32 ? 1024 : 4096; }
+constexpr int lds_slots() { return G == G_SUM_F32 ? 1024 : 4096; }
+inline int lds_slots_of(int g) { return g == G_SUM_F32 ? 1024 : 4096; }
 constexpr int kPartThreads = 1024;
 
 struct Table {
@@ -510,12 +509,12 @@ struct LdsTable {
 
 // Direct path: every workgroup sweeps the rows grid-stride into one LDS table.
 template <int KD, int VD, int G>
-__global__ void __launch_bounds__(kThreads) gb_aggregate_kernel(Args a) {
-  __shared__ LdsTable<G, lds_slots<G>(), kThreads> tab;
+__global__ void __launch_bounds__(kDirectThreads) gb_aggregate_kernel(Args a) {
+  __shared__ LdsTable<G, lds_slots<G>(), kDirectThreads> tab;
   tab.clear();
   __syncthreads();
-  tab.template fold_rows<KD, VD>(a.t, a.keys, a.vals, (int64_t)blockIdx.x * kThreads + threadIdx.x, a.n,
-                                 (int64_t)gridDim.x * kThreads);
+  tab.template fold_rows<KD, VD>(a.t, a.keys, a.vals, (int64_t)blockIdx.x * kDirectThreads + threadIdx.x, a.n,
+                                 (int64_t)gridDim.x * kDirectThreads);
   __syncthreads();
   tab.flush(a.t);
 }
@@ -527,7 +526,7 @@ __global__ void __launch_bounds__(kThreads) gb_aggregate_kernel(Args a) {
 // whatever the partition sizes.
 template <int KD, int VD, int G>
 __global__ void __launch_bounds__(kPartThreads) gb_aggregate_part_kernel(Args a) {
-  __shared__ LdsTable<G, part_slots<G>(), kPartThreads> tab;
+  __shared__ LdsTable<G, lds_slots<G>(), kPartThreads> tab;
   const int P = 1 << a.pt.bits;
   int64_t r = a.n * (int64_t)blockIdx.x / gridDim.x;
   const int64_t r1 = a.n * ((int64_t)blockIdx.x + 1) / gridDim.x;
@@ -843,12 +842,20 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   while (cap < 2 * max_groups) cap <<= 1;
   const int64_t slots = cap + 1;
   const bool dig = g == G_SUM_F32;
-  // partitioned when a direct-path LDS table would be more than half full
-  // of groups; a partition then holds at most half of its (larger) table
+  // Linear probing slows sharply once a table is half full (a wave waits
+  // for its longest probe chain), so tables are kept a quarter full: the
+  // direct path up to a quarter of its LDS table, partitions a quarter of
+  // theirs -- or half, where a quarter would need more partitions than the
+  // LDS-tiled scatter handles.
   int bits = 0;
-  if (max_groups > lds_slots_of(g) / 2) {
-    const int64_t per_part = part_slots_of(g) / 2;
-    while (bits < kMaxPartBits && (per_part << bits) < max_groups) ++bits;
+  if (max_groups > lds_slots_of(g) / 4) {
+    auto bits_for = [max_groups](int64_t per_part) {
+      int b = 0;
+      while (b < kMaxPartBits && (per_part << b) < max_groups) ++b;
+      return b;
+    };
+    bits = bits_for(lds_slots_of(g) / 4);
+    if (bits > kTileMaxBits) bits = bits_for(lds_slots_of(g) / 2);
     bits = std::max(bits, kMinPartBits);  // few partitions would serialise the counting atomics
   }
   const int64_t P = bits ? (int64_t)1 << bits : 0;
@@ -897,7 +904,7 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   // aggregation grids are sized to what the chip holds at once (no second, mostly idle wave of workgroups)
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, agg_kernel(key_dtype, val_dtype, g, bits != 0),
-                                                   bits ? kPartThreads : kThreads, 0) !=
+                                                   bits ? kPartThreads : kDirectThreads, 0) !=
           hipSuccess ||
       nb < 1) {
     (void)hipGetLastError();
@@ -939,8 +946,9 @@ int agg_groupby_run(agg_groupby_t p, const void* keys, const void* vals, int64_t
   rc = launch(init_kernel(p->gop), (int)table_grid, kThreads, &a.t, stream);
   if (rc != AGG_OK) return rc;
   if (n > 0 && p->pt.bits == 0) {
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, kThreads * 16), (int64_t)cu * p->agg_blocks));
-    rc = launch(agg_kernel(p->key_dtype, p->val_dtype, p->gop, false), (int)grid, kThreads, &a, stream);
+    const int64_t grid =
+        std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, kDirectThreads * 16), (int64_t)cu * p->agg_blocks));
+    rc = launch(agg_kernel(p->key_dtype, p->val_dtype, p->gop, false), (int)grid, kDirectThreads, &a, stream);
     if (rc != AGG_OK) return rc;
   } else if (n > 0) {
     const int64_t P = (int64_t)1 << p->pt.bits;
