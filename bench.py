@@ -288,6 +288,7 @@ def bench_serve(agg, torch, host_i32, dev_i32, full=False):
         arena_h = torch.empty(n_max, dtype=torch.int32, pin_memory=True)
         import datagen
         datagen.fill_ptr(arena_h.data_ptr(), n_max, "i32", "uniform", 13)
+        log(f"serving arena: {n_max} int32 items in pinned host memory")
     cap = 55e9 / (0.7 * mean_bytes(10_000, n_max, 4))
     rate = 0.8 * cap
     specs = request_stream(nreq, seed=13, n_min=10_000, n_max=n_max, rate_per_s=rate, resident_frac=0.3,
@@ -298,7 +299,9 @@ def bench_serve(agg, torch, host_i32, dev_i32, full=False):
     budget = 200 * 10**9
     free, _ = torch.cuda.mem_get_info()
     budget = min(budget, int(free - (8 << 30)))
-    srv = agg.Server(hbm_budget_bytes=budget, max_slots=8, cache_shipped=False, max_shipping=2)
+    srv = agg.Server(hbm_budget_bytes=budget, max_slots=8, cache_shipped=False, max_shipping=2,
+                     progress_every=1000 if full else 0)
+    log(f"serving {nreq} requests (lengths up to {n_max}) at {rate:.1f}/s")
     t0 = time.time()
     results, stats, sm = srv.run(reqs)
     wall = time.time() - t0

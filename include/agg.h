@@ -358,7 +358,8 @@ typedef struct agg_serve_config {
     int32_t max_shipping;      /* shipped requests in flight at once, 1..max_slots: they
                                   share one PCIe link, so more only stretches each of them
                                   and holds slots that resident requests could use */
-    int32_t reserved;
+    int32_t progress_every;    /* > 0: agg_serve_run writes a line to stderr each time this
+                                  many more requests have completed (long runs); 0: silent */
 } agg_serve_config;
 
 typedef struct agg_request_stats {

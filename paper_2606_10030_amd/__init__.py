@@ -77,7 +77,7 @@ class Request(ctypes.Structure):
 class ServeConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
                 ("cache_shipped", ctypes.c_int32), ("chunk_bytes", ctypes.c_int64),
-                ("max_shipping", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_shipping", ctypes.c_int32), ("progress_every", ctypes.c_int32)]
 
 
 class RequestStats(ctypes.Structure):
@@ -572,17 +572,18 @@ def _requests(reqs) -> "ctypes.Array":
     return arr
 
 
-def _config(hbm_budget_bytes, max_slots, cache_shipped, chunk_bytes, max_shipping) -> ServeConfig:
+def _config(hbm_budget_bytes, max_slots, cache_shipped, chunk_bytes, max_shipping, progress_every=0) -> ServeConfig:
     ms = min(int(max_slots), 2) if max_shipping is None else int(max_shipping)
-    return ServeConfig(int(hbm_budget_bytes), int(max_slots), 1 if cache_shipped else 0, int(chunk_bytes), ms, 0)
+    return ServeConfig(int(hbm_budget_bytes), int(max_slots), 1 if cache_shipped else 0, int(chunk_bytes), ms,
+                       int(progress_every))
 
 
 class Server:
     """agg_serve_create / agg_serve_run: continuous admission of requests on the GPU."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, cache_shipped: bool = True,
-                 chunk_bytes: int = 64 << 20, max_shipping: Optional[int] = None):
-        self.cfg = _config(hbm_budget_bytes, max_slots, cache_shipped, chunk_bytes, max_shipping)
+                 chunk_bytes: int = 64 << 20, max_shipping: Optional[int] = None, progress_every: int = 0):
+        self.cfg = _config(hbm_budget_bytes, max_slots, cache_shipped, chunk_bytes, max_shipping, progress_every)
         h = ctypes.c_void_p()
         _check(lib().agg_serve_create(ctypes.byref(h), ctypes.byref(self.cfg)), "agg_serve_create")
         self._h = h

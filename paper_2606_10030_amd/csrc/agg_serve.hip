@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <limits>
@@ -189,6 +190,10 @@ class Scheduler {
         nship -= j.ship ? 1 : 0;
         ++finished;
         progress = true;
+        if (cfg_.progress_every > 0 && finished % cfg_.progress_every == 0) {
+          std::fprintf(stderr, "agg_serve: %d of %d requests done at %.3f s\n", finished, n, rs.done_s - first);
+          std::fflush(stderr);
+        }
       }
       // admissions, in arrival order; a shipped request that does not fit
       // blocks later shipped requests (FIFO for HBM) but not resident or
@@ -295,8 +300,12 @@ class Scheduler {
 // Chunks of a shipped column in flight per slot.  The host drives the
 // pipeline: it starts the scan of a chunk only after seeing its copy finish,
 // and then starts the next copy, so no compute queue ever holds a wait on a
-// PCIe copy (with more streams than hardware queues, such a wait would also
-// stall unrelated requests queued behind it).
+// PCIe copy.  Each in-flight chunk has a copy stream of its own, and the host
+// sees its completion by querying that stream: an event recorded after a
+// copy puts exactly such a wait into a hardware queue that other streams
+// share (with more streams than hardware queues), and measured, it held a
+// tiny kernel on an unrelated stream for the whole copy backlog (100+ ms)
+// where the stream query left it at 15 us.
 constexpr int kPipe = 4;
 
 struct SlotRun {
@@ -411,8 +420,7 @@ struct agg_server_s {
   char* arena = nullptr;  // hbm_budget_bytes of device memory
   int slots = 0;
   hipStream_t comp[kMaxSlots] = {};
-  hipStream_t copy[kMaxSlots] = {};
-  hipEvent_t copied[kMaxSlots][kPipe] = {};
+  hipStream_t copy[kMaxSlots][kPipe] = {};  // one chunk in flight on each
   hipEvent_t done[kMaxSlots] = {};
   uint64_t* part = nullptr;       // slots x kSegTarget partial slots
   agg_result* res_host = nullptr;  // slots results, page-locked host memory
@@ -424,9 +432,8 @@ void server_release(agg_server_s* s) {
   if (!s) return;
   for (int i = 0; i < s->slots; ++i) {
     if (s->comp[i]) (void)hipStreamDestroy(s->comp[i]);
-    if (s->copy[i]) (void)hipStreamDestroy(s->copy[i]);
     for (int k = 0; k < kPipe; ++k)
-      if (s->copied[i][k]) (void)hipEventDestroy(s->copied[i][k]);
+      if (s->copy[i][k]) (void)hipStreamDestroy(s->copy[i][k]);
     if (s->done[i]) (void)hipEventDestroy(s->done[i]);
   }
   if (s->part) (void)hipFree(s->part);
@@ -442,7 +449,7 @@ agg::serve::HipExecutor::HipExecutor(agg_server_s* s)
 
 int agg::serve::HipExecutor::fail(int slot, int rc) {
   // let anything already queued for this slot drain before its memory is reused
-  (void)hipStreamSynchronize(s_->copy[slot]);
+  for (int k = 0; k < kPipe; ++k) (void)hipStreamSynchronize(s_->copy[slot][k]);
   (void)hipStreamSynchronize(s_->comp[slot]);
   (void)hipGetLastError();
   return rc;
@@ -453,8 +460,9 @@ int agg::serve::HipExecutor::copy_chunk(int slot, int64_t k) {
   const int64_t lo = k * r.cs, hi = std::min(r.nseg, lo + r.cs);
   const int64_t b0 = lo * r.seg_bytes;
   const int64_t nb = std::min(r.bytes, hi * r.seg_bytes) - b0;
-  hipError_t e = hipMemcpyAsync(r.dst + b0, r.host + b0, (size_t)nb, hipMemcpyHostToDevice, s_->copy[slot]);
-  if (e == hipSuccess) e = hipEventRecord(s_->copied[slot][k % kPipe], s_->copy[slot]);
+  // chunk k + kPipe is issued on this stream only after chunk k was seen complete
+  const hipError_t e =
+      hipMemcpyAsync(r.dst + b0, r.host + b0, (size_t)nb, hipMemcpyHostToDevice, s_->copy[slot][k % kPipe]);
   if (e != hipSuccess) {
     record_hip_error((int32_t)e);
     return AGG_E_HIP;
@@ -534,7 +542,7 @@ int agg::serve::HipExecutor::poll(int slot) {
   SlotRun& r = run_[slot];
   if (r.ship && !r.combined) {
     while (r.next_scan < r.next_copy) {
-      const hipError_t e = hipEventQuery(s_->copied[slot][r.next_scan % kPipe]);
+      const hipError_t e = hipStreamQuery(s_->copy[slot][r.next_scan % kPipe]);
       if (e == hipErrorNotReady) break;
       if (e != hipSuccess) {
         record_hip_error((int32_t)e);
@@ -595,13 +603,10 @@ int agg_serve_create(agg_server_t* out, const agg_serve_config* cfg) {
   }
   for (int i = 0; i < cfg->max_slots; ++i) {
     s->slots = i + 1;
-    if ((e = hipStreamCreateWithFlags(&s->comp[i], hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&s->copy[i], hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&s->copied[i][0], hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&s->copied[i][1], hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&s->copied[i][2], hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&s->copied[i][3], hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&s->done[i], hipEventDisableTiming)) != hipSuccess) {
+    e = hipStreamCreateWithFlags(&s->comp[i], hipStreamNonBlocking);
+    for (int k = 0; k < kPipe && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&s->copy[i][k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->done[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
       record_hip_error((int32_t)e);
       return fail(AGG_E_HIP);
     }
