@@ -34,8 +34,8 @@
  *   - Work is asynchronous on the caller's HIP stream (`stream` is a
  *     hipStream_t; NULL = the legacy default stream).  A result is valid once
  *     that stream has been synchronised.
- *   - A plan or batch is not re-entrant: two calls that overlap in time (for
- *     instance on two streams) must use two plans.
+ *   - A plan, batch, group-by plan or server is not re-entrant: two calls that
+ *     overlap in time (for instance on two streams) must use two of them.
  */
 #ifndef AGG_H
 #define AGG_H
