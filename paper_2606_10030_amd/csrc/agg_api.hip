@@ -718,16 +718,30 @@ int agg_batch_plan(agg_batch_t* out, const agg_col* cols, int32_t ncols, const a
     d.prec_used = (c.dtype == AGG_F32 && (c.op == AGG_SUM || c.op == AGG_AVG)) ? c.prec : -1;
     d.aligned = (reinterpret_cast<uintptr_t>(c.ptr) & 15) == 0;
     slots += s.nseg;
+    if (slots > (int64_t)UINT32_MAX) return AGG_E_INVALID;  // partial slots are indexed by 32 bits
     const int64_t per = std::max<int64_t>(1, kItemBytes / s.seg_bytes);
     for (int64_t lo = 0; lo < s.nseg; lo += per) {
-      WorkItem it;
-      it.col = i;
-      it.seg_lo = (int32_t)lo;
-      it.seg_hi = (int32_t)std::min<int64_t>(s.nseg, lo + per);
-      it.reserved = 0;
+      WorkItem it{};
+      it.ptr = d.ptr;
+      it.col_bytes = d.col_bytes;
+      it.part_off = (uint32_t)d.part_off;
+      it.seg_lo = (uint16_t)lo;
+      it.seg_hi = (uint16_t)std::min<int64_t>(s.nseg, lo + per);
+      it.seg_log2 = (uint8_t)__builtin_ctzll((uint64_t)d.seg_bytes);
+      it.kind = (uint8_t)d.kind;
+      it.aligned = (uint8_t)d.aligned;
       items.push_back(it);
     }
   }
+  // Largest items first: waves take items w, w + P, w + 2P, ..., so this
+  // evens out their totals (the order decides nothing about the results: each
+  // segment's partial has its own slot and columns merge in canonical order).
+  auto item_bytes = [](const WorkItem& it) {
+    const int64_t sb = (int64_t)1 << it.seg_log2;
+    return std::min(it.col_bytes, it.seg_hi * sb) - it.seg_lo * sb;
+  };
+  std::stable_sort(items.begin(), items.end(),
+                   [&](const WorkItem& x, const WorkItem& y) { return item_bytes(x) > item_bytes(y); });
 
   agg_batch_s* b = new (std::nothrow) agg_batch_s();
   if (!b) return AGG_E_NOMEM;
@@ -823,7 +837,7 @@ int agg_batch_autotune(agg_batch_t b, void* stream_v, agg_tune* best, double* be
     HIPCHK(e);
   }
   int rc = AGG_OK;
-  for (int u : {8, 16, 32}) {
+  for (int u : {4, 8, 16}) {  // 32 spills registers in the batch kernel
     for (auto& p : wb) {
       agg_tune t = b->tune;
       t.unroll = u;

@@ -97,11 +97,19 @@ struct BatchColDev {
 
 // A run of whole segments [seg_lo, seg_hi) of one column: the unit of work
 // of the persistent batch kernel.
+// A run of whole segments of one column, with the column fields the scan
+// needs copied in (32 bytes), so a wave reads one record instead of an item
+// and then its column.
 struct WorkItem {
-  int32_t col;
-  int32_t seg_lo;
-  int32_t seg_hi;
-  int32_t reserved;
+  const char* ptr;       // column base
+  int64_t col_bytes;
+  uint32_t part_off;     // first 8-byte partial slot of the column
+  uint16_t seg_lo;       // segments [seg_lo, seg_hi) (a column has at most 8192)
+  uint16_t seg_hi;
+  uint8_t seg_log2;      // seg_bytes = 2^seg_log2
+  uint8_t kind;
+  uint8_t aligned;       // ptr is 16-byte aligned
+  uint8_t pad[5];
 };
 
 struct BatchArgs {

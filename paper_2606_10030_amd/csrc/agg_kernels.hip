@@ -137,45 +137,70 @@ __global__ void __launch_bounds__(1024) packed_scan_kernel(PackedArgs a) {
 
 // ------------------------------------------------------------ batch
 template <int K, int U, bool NT>
-__device__ __forceinline__ void batch_item(const BatchColDev& c, const WorkItem& it, uint64_t* slots,
-                                           int lane) {
+__device__ __forceinline__ void batch_item(const WorkItem& it, uint64_t* slots, int lane) {
   using F = Fold<K>;
   using P = typename F::part;
-  P* part = reinterpret_cast<P*>(slots + c.part_off);
+  P* part = reinterpret_cast<P*>(slots + it.part_off);
+  const int64_t seg_bytes = (int64_t)1 << it.seg_log2;
   for (int64_t j = it.seg_lo; j < it.seg_hi; ++j) {
-    const int64_t begin = j * c.seg_bytes;
-    const int64_t valid = c.col_bytes - begin < c.seg_bytes ? c.col_bytes - begin : c.seg_bytes;
-    typename F::acc acc = c.aligned ? fold_segment<K, U, NT, true>(c.ptr + begin, valid, lane)
-                                    : fold_segment<K, 4, false, false>(c.ptr + begin, valid, lane);
+    const int64_t begin = j * seg_bytes;
+    const int64_t valid = it.col_bytes - begin < seg_bytes ? it.col_bytes - begin : seg_bytes;
+    typename F::acc acc = it.aligned ? fold_segment<K, U, NT, true>(it.ptr + begin, valid, lane)
+                                     : fold_segment<K, 4, false, false>(it.ptr + begin, valid, lane);
     acc = wave_reduce(acc, AccMerge<K>());
     if (lane == 0) part[j] = F::to_part(acc);
   }
 }
 
+// A wave's items are i = wave, wave + P, wave + 2P, ... (P waves).  It reads
+// their records 64 at a time, one per lane, and takes each out of its lane
+// with readlane: one memory round trip per 64 items instead of one per item.
 template <int U, bool NT>
 __global__ void __launch_bounds__(1024) batch_scan_kernel(BatchArgs a) {
+  static_assert(sizeof(WorkItem) == 32, "a work record is two 16-byte words");
   const int lane = threadIdx.x & (kWave - 1);
   const int W = blockDim.x / kWave;
   const int64_t nwaves = (int64_t)gridDim.x * W;
   const int64_t wave = (int64_t)blockIdx.x * W + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  for (int64_t i = wave; i < a.nitems; i += nwaves) {
-    const WorkItem it = a.items[i];
-    const BatchColDev c = a.cols[it.col];
-    switch (c.kind) {
-      case K_SUM_I32: batch_item<K_SUM_I32, U, NT>(c, it, a.part, lane); break;
-      case K_MIN_I32: batch_item<K_MIN_I32, U, NT>(c, it, a.part, lane); break;
-      case K_MAX_I32: batch_item<K_MAX_I32, U, NT>(c, it, a.part, lane); break;
-      case K_SUM_I64: batch_item<K_SUM_I64, U, NT>(c, it, a.part, lane); break;
-      case K_MIN_I64: batch_item<K_MIN_I64, U, NT>(c, it, a.part, lane); break;
-      case K_MAX_I64: batch_item<K_MAX_I64, U, NT>(c, it, a.part, lane); break;
-      case K_SUM_F32_PLAIN: batch_item<K_SUM_F32_PLAIN, U, NT>(c, it, a.part, lane); break;
-      case K_SUM_F32_F64C: batch_item<K_SUM_F32_F64C, U, NT>(c, it, a.part, lane); break;
-      case K_SUM_F32_NEU: batch_item<K_SUM_F32_NEU, U, NT>(c, it, a.part, lane); break;
-      case K_MIN_F32: batch_item<K_MIN_F32, U, NT>(c, it, a.part, lane); break;
-      case K_MAX_F32: batch_item<K_MAX_F32, U, NT>(c, it, a.part, lane); break;
-      case K_COUNT_4: batch_item<K_COUNT_4, U, NT>(c, it, a.part, lane); break;
-      case K_COUNT_8: batch_item<K_COUNT_8, U, NT>(c, it, a.part, lane); break;
-      default: break;
+  for (int64_t base = wave; base < a.nitems; base += kWave * nwaves) {
+    const int64_t mine = base + lane * nwaves;
+    u32x4 w0 = {0, 0, 0, 0}, w1 = w0;
+    if (mine < a.nitems) {
+      const u32x4* rec = reinterpret_cast<const u32x4*>(a.items + mine);
+      w0 = rec[0];
+      w1 = rec[1];
+    }
+    const int64_t left = (a.nitems - base + nwaves - 1) / nwaves;
+    const int cnt = left < kWave ? (int)left : kWave;
+    for (int l = 0; l < cnt; ++l) {
+      auto rd = [l](uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); };
+      auto rd64 = [&](uint32_t lo, uint32_t hi) { return (int64_t)(((uint64_t)rd(hi) << 32) | rd(lo)); };
+      WorkItem it;
+      it.ptr = reinterpret_cast<const char*>(rd64(w0[0], w0[1]));
+      it.col_bytes = rd64(w0[2], w0[3]);
+      it.part_off = rd(w1[0]);
+      const uint32_t range = rd(w1[1]), meta = rd(w1[2]);
+      it.seg_lo = (uint16_t)(range & 0xFFFFu);
+      it.seg_hi = (uint16_t)(range >> 16);
+      it.seg_log2 = (uint8_t)(meta & 0xFFu);
+      it.kind = (uint8_t)((meta >> 8) & 0xFFu);
+      it.aligned = (uint8_t)((meta >> 16) & 0xFFu);
+      switch (it.kind) {
+        case K_SUM_I32: batch_item<K_SUM_I32, U, NT>(it, a.part, lane); break;
+        case K_MIN_I32: batch_item<K_MIN_I32, U, NT>(it, a.part, lane); break;
+        case K_MAX_I32: batch_item<K_MAX_I32, U, NT>(it, a.part, lane); break;
+        case K_SUM_I64: batch_item<K_SUM_I64, U, NT>(it, a.part, lane); break;
+        case K_MIN_I64: batch_item<K_MIN_I64, U, NT>(it, a.part, lane); break;
+        case K_MAX_I64: batch_item<K_MAX_I64, U, NT>(it, a.part, lane); break;
+        case K_SUM_F32_PLAIN: batch_item<K_SUM_F32_PLAIN, U, NT>(it, a.part, lane); break;
+        case K_SUM_F32_F64C: batch_item<K_SUM_F32_F64C, U, NT>(it, a.part, lane); break;
+        case K_SUM_F32_NEU: batch_item<K_SUM_F32_NEU, U, NT>(it, a.part, lane); break;
+        case K_MIN_F32: batch_item<K_MIN_F32, U, NT>(it, a.part, lane); break;
+        case K_MAX_F32: batch_item<K_MAX_F32, U, NT>(it, a.part, lane); break;
+        case K_COUNT_4: batch_item<K_COUNT_4, U, NT>(it, a.part, lane); break;
+        case K_COUNT_8: batch_item<K_COUNT_8, U, NT>(it, a.part, lane); break;
+        default: break;
+      }
     }
   }
 }
