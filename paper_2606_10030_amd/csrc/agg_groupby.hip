@@ -11,8 +11,8 @@
 // per (workgroup, key) instead of one per row.
 //
 // Two paths, chosen from the plan's max_groups:
-//  * direct: every workgroup's LDS table holds all the groups at a quarter of
-//    its slots; workgroups stride over the rows.
+//  * direct: every workgroup's LDS table holds all the groups in at most half
+//    of its slots; workgroups stride over the rows.
 //  * partitioned (more groups than an LDS table holds): rows are processed in
 //    chunks; each chunk is radix-partitioned on the top bits of the key's
 //    hash (histogram, prefix sums, scatter into a staging copy), so that one
@@ -464,8 +464,12 @@ struct LdsTable {
         const int64_t k = kk[r];
         int s = -1;
         if (k != kEmpty) {
-          int h = (int)(mix64((uint64_t)k) & (L - 1));
-          for (int p = 0; p < kLdsProbes; ++p, h = (h + 1) & (L - 1)) {
+          // double hashing: an odd step from the hash's high half, so probe
+          // chains do not cluster (a wave waits for its longest chain)
+          const uint64_t hk = mix64((uint64_t)k);
+          int h = (int)(hk & (L - 1));
+          const int step = (int)(((hk >> 32) | 1) & (L - 1));
+          for (int p = 0; p < kLdsProbes; ++p, h = (h + step) & (L - 1)) {
             const int64_t cur = key[h];
             if (cur == k) { s = h; break; }
             if (cur == kEmpty) {
@@ -771,20 +775,18 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   while (cap < 2 * max_groups) cap <<= 1;
   const int64_t slots = cap + 1;
   const bool dig = g == G_SUM_F32;
-  // Linear probing slows sharply once a table is half full (a wave waits
-  // for its longest probe chain), so tables are kept a quarter full: the
-  // direct path up to a quarter of its LDS table, partitions a quarter of
-  // theirs -- or half, where a quarter would need more partitions than the
-  // LDS-tiled scatter handles.
+  // LDS tables are filled at most half (with double hashing a half-full
+  // table still probes fast; measured, linear probing slowed sharply past a
+  // quarter): the direct path up to half of its table, partitions sized for
+  // half of theirs.
   int bits = 0;
-  if (max_groups > lds_slots_of(g) / 4) {
+  if (max_groups > lds_slots_of(g) / 2) {
     auto bits_for = [max_groups](int64_t per_part) {
       int b = 0;
       while (b < kMaxPartBits && (per_part << b) < max_groups) ++b;
       return b;
     };
-    bits = bits_for(lds_slots_of(g) / 4);
-    if (bits > kTileMaxBits) bits = bits_for(lds_slots_of(g) / 2);
+    bits = bits_for(lds_slots_of(g) / 2);
     bits = std::max(bits, kMinPartBits);  // few partitions would serialise the counting atomics
   }
   const int64_t P = bits ? (int64_t)1 << bits : 0;
