@@ -125,43 +125,83 @@ def groupby_profile_mode(cards):
 def bench_energy(agg, torch, dev_i32, host_i32, stream):
     """Joules per aggregation from the GPU's energy accumulator (amdsmi), for
     the on-device SUM of a 2^30-item int32 column and the same SUM end to end
-    (zero-copy from pinned host memory); idle power measured first and also
-    subtracted ("above idle")."""
+    (zero-copy from pinned host memory), plus idle power.
+
+    The accumulator advances about once a second, so each figure comes from a
+    window of several seconds: the host keeps the GPU busy with scans issued
+    in batches and notes the time of every counter update; average power is
+    taken between the first and the last update that both fall inside the
+    busy window (never across its edges), and energy per scan = that power x
+    the measured time per scan."""
     try:
         import amdsmi
         amdsmi.amdsmi_init()
         h = amdsmi.amdsmi_get_processor_handles()[0]
+        res = amdsmi.amdsmi_get_energy_count(h)["counter_resolution"]
     except Exception as ex:  # telemetry not available on this host
         return {"available": False, "reason": f"{type(ex).__name__}: {ex}"[:200]}
 
-    def joules():
-        e = amdsmi.amdsmi_get_energy_count(h)
-        return e["energy_accumulator"] * e["counter_resolution"] * 1e-6
+    def counter():
+        return amdsmi.amdsmi_get_energy_count(h)["energy_accumulator"]
 
-    out = {"available": True, "source": "amdsmi energy accumulator (whole GPU)"}
+    def power(edges, t_lo, t_hi):
+        inside = [(t, v) for t, v in edges if t_lo < t < t_hi]
+        if len(inside) < 2:
+            return None
+        (ta, va), (tb, vb) = inside[0], inside[-1]
+        return (vb - va) * res * 1e-6 / (tb - ta)
+
+    def watch(edges, last):
+        v = counter()
+        if v != last[0]:
+            edges.append((time.perf_counter(), v))
+            last[0] = v
+
+    out = {"available": True, "source": "amdsmi energy accumulator (whole GPU), updates about once a second",
+           "method": "power between counter updates inside a 3.5-5 s window, x time per scan"}
     torch.cuda.synchronize()
-    j0, t0 = joules(), time.perf_counter()
-    time.sleep(1.0)
-    idle_w = (joules() - j0) / (time.perf_counter() - t0)
-    out["idle_W"] = round(idle_w, 1)
+    edges, last = [], [counter()]
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 3.5:
+        watch(edges, last)
+        time.sleep(0.001)
+    idle_w = power(edges, t0, time.perf_counter())
+    out["idle_W"] = None if idle_w is None else round(idle_w, 1)
     n = dev_i32.numel()
     o = torch.zeros(32, dtype=torch.uint8, device="cuda")
-    for label, src, col, reps in (("on_device", "device", dev_i32, 3000), ("end_to_end_zerocopy", "zerocopy", host_i32, 25)):
+    for label, src, col, batch in (("on_device", "device", dev_i32, 200), ("end_to_end_zerocopy", "zerocopy", host_i32, 2)):
         p = agg.Plan("i32", "sum", max_n=n, src=src)
         p.enqueue(col, o, stream=stream)
         torch.cuda.synchronize()
-        j0, t0 = joules(), time.perf_counter()
-        for _ in range(reps):
-            p.enqueue(col, o, stream=stream)
-        torch.cuda.synchronize()
-        dt, dj = time.perf_counter() - t0, joules() - j0
+        edges, last, pending, scans = [], [counter()], [], 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 5.0 or pending:
+            if time.perf_counter() - t0 < 5.0 and len(pending) < 3:
+                for _ in range(batch):
+                    p.enqueue(col, o, stream=stream)
+                ev = torch.cuda.Event()
+                ev.record(stream)
+                pending.append(ev)
+                scans += batch
+            else:
+                watch(edges, last)
+                if pending and pending[0].query():
+                    pending.pop(0)
+                else:
+                    time.sleep(0.0005)
+        t1 = time.perf_counter()
         p.close()
-        per = dj / reps
-        above = (dj - idle_w * dt) / reps
+        per_scan_s = (t1 - t0) / scans
+        busy_w = power(edges, t0, t1)
         gb = n * 4 / 1e9
-        out[label] = {"J_per_scan": round(per, 4), "J_per_scan_above_idle": round(above, 4),
-                      "J_per_GB": round(per / gb, 4), "avg_W": round(dj / dt, 1), "scans": reps,
-                      "seconds": round(dt, 2),
+        if busy_w is None:
+            out[label] = {"scans": scans, "seconds": round(t1 - t0, 2), "J_per_scan": None}
+            continue
+        per = busy_w * per_scan_s
+        out[label] = {"J_per_scan": round(per, 4),
+                      "J_per_scan_above_idle": None if idle_w is None else round((busy_w - idle_w) * per_scan_s, 4),
+                      "J_per_GB": round(per / gb, 4), "avg_W": round(busy_w, 1), "scans": scans,
+                      "seconds": round(t1 - t0, 2), "ms_per_scan": round(per_scan_s * 1e3, 3),
                       "J_for_1.2e9_items": round(per * 1.2e9 / n, 4)}
     try:
         amdsmi.amdsmi_shut_down()
