@@ -43,14 +43,14 @@ constexpr int64_t kEmpty = INT64_MIN;
 constexpr int kThreads = 256;
 constexpr int kLdsProbes = 16;
 constexpr int kAggRows = 8;           // rows whose loads a thread keeps in flight
-constexpr int kMaxPartBits = 14;      // at most 16384 partitions
+constexpr int kMaxPartBits = 14;      // at most 16384 (sub-)partitions
 constexpr int kMinPartBits = 5;       // at least 32
 constexpr int64_t kChunkRows = (int64_t)1 << 26;
 constexpr int64_t kHistRows = (int64_t)1 << 16;    // rows per histogram / scatter workgroup
 constexpr int kMaxHistWg = (int)(kChunkRows / kHistRows);
 constexpr int kScanThreads = 1024;
-constexpr int kTileThreads = 1024;    // tiled scatter: rows staged in LDS per tile
-constexpr int kTileMaxBits = 11;      // tiled scatter for up to 2048 partitions
+constexpr int kTileThreads = 1024;    // scatter: rows staged in LDS per tile
+constexpr int kTileMaxBits = 11;      // scatter into at most 2048 partitions
 // rows per tile: 8192, or 4096 where 8-byte keys and values would not fit LDS
 template <int KD, int VD, bool HASV>
 constexpr int tile_rows() { return (KD == AGG_I64 && VD == AGG_I64 && HASV) ? 4096 : 8192; }
@@ -84,7 +84,8 @@ struct Part {
   uint32_t* start;     // [P + 1] first staged row of each partition
   void* pk;            // staged keys (kChunkRows)
   void* pv;            // staged values (none for COUNT)
-  int32_t bits;        // log2 of the number of partitions
+  int32_t bits;        // log2 of the number of partitions the rows are scattered into
+  int32_t sub_bits;    // log2 of the aggregation passes over each of them (one per sub-partition)
   int32_t g1;          // histogram / scatter workgroups of this chunk
   int64_t rows_per_wg; // rows each of them covers
 };
@@ -300,33 +301,11 @@ __global__ void __launch_bounds__(kScanThreads) gb_scan_tot_kernel(Args a) {
   if (threadIdx.x == kScanThreads - 1) a.pt.start[P] = run;  // the last thread ends on the total
 }
 
-// The same rows per workgroup as the histogram: each row lands at its
-// partition's start + this workgroup's prefix + a slot taken by an LDS atomic.
-template <int KD, int VD, bool HASV>
-__global__ void __launch_bounds__(kThreads) gb_scatter_kernel(Args a) {
-  extern __shared__ uint32_t cur[];
-  const int P = 1 << a.pt.bits;
-  for (int e = threadIdx.x; e < P; e += kThreads)
-    cur[e] = a.pt.start[e] + a.pt.hist[(int64_t)e * a.pt.g1 + blockIdx.x];
-  __syncthreads();
-  const int64_t lo = (int64_t)blockIdx.x * a.pt.rows_per_wg;
-  const int64_t hi = std::min<int64_t>(lo + a.pt.rows_per_wg, a.n);
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
-    const int64_t k = load_key<KD>(a.keys, i);
-    const uint32_t pos = atomicAdd(&cur[part_of(k, a.pt.bits)], 1u);
-    if ((int64_t)pos >= a.n) continue;  // cannot happen: counts match the histogram
-    if constexpr (KD == AGG_I32) static_cast<int32_t*>(a.pt.pk)[pos] = (int32_t)k;
-    else static_cast<int64_t*>(a.pt.pk)[pos] = k;
-    if constexpr (HASV) {
-      if constexpr (VD == AGG_I64) static_cast<int64_t*>(a.pt.pv)[pos] = static_cast<const int64_t*>(a.vals)[i];
-      else static_cast<uint32_t*>(a.pt.pv)[pos] = static_cast<const uint32_t*>(a.vals)[i];
-    }
-  }
-}
-
-// Scatter through LDS: each tile of rows is counting-sorted by
-// partition in LDS first, so the rows of one partition leave as one
-// contiguous run (coalesced stores) instead of one scattered store per row.
+// Each row lands at its partition's start + this workgroup's prefix (the
+// histogram workgroup of the same rows) + its rank among the partition's
+// rows of this workgroup.  Each tile of rows is counting-sorted by partition
+// in LDS first, so the rows of one partition leave as one contiguous run
+// (coalesced stores) instead of one scattered store per row.
 template <int KD, int VD, bool HASV>
 __global__ void __launch_bounds__(kTileThreads) gb_scatter_tiled_kernel(Args a) {
   using KT = typename std::conditional<KD == AGG_I32, int32_t, int64_t>::type;
@@ -436,11 +415,12 @@ struct LdsTable {
     }
   }
 
-  // Rows first, first + step, ... below last; a row whose key finds no slot
-  // within kLdsProbes goes to the global table.
+  // Rows first, first + step, ... below last whose key hash has the bits
+  // (hash >> sub_shift) & sub_mask equal to sub; a row whose key finds no
+  // slot within kLdsProbes goes to the global table.
   template <int KD, int VD>
   __device__ void fold_rows(const Table& t, const void* keys, const void* vals, int64_t first, int64_t last,
-                            int64_t step) {
+                            int64_t step, uint32_t sub_shift, uint32_t sub_mask, uint32_t sub) {
     constexpr int R = kAggRows;
     for (int64_t base = first; base < last; base += step * R) {
       int64_t kk[R], ivv[R];  // R rows' loads in flight before any is folded
@@ -462,11 +442,12 @@ struct LdsTable {
       for (int r = 0; r < R; ++r) {
         if (base + r * step >= last) break;
         const int64_t k = kk[r];
+        const uint64_t hk = mix64((uint64_t)k);
+        if (((uint32_t)(hk >> sub_shift) & sub_mask) != sub) continue;  // another pass's row
         int s = -1;
         if (k != kEmpty) {
           // double hashing: an odd step from the hash's high half, so probe
           // chains do not cluster (a wave waits for its longest chain)
-          const uint64_t hk = mix64((uint64_t)k);
           int h = (int)(hk & (L - 1));
           const int step = (int)(((hk >> 32) | 1) & (L - 1));
           for (int p = 0; p < kLdsProbes; ++p, h = (h + step) & (L - 1)) {
@@ -517,7 +498,7 @@ __global__ void __launch_bounds__(kDirectThreads) gb_aggregate_kernel(Args a) {
   tab.clear();
   __syncthreads();
   tab.template fold_rows<KD, VD>(a.t, a.keys, a.vals, (int64_t)blockIdx.x * kDirectThreads + threadIdx.x, a.n,
-                                 (int64_t)gridDim.x * kDirectThreads);
+                                 (int64_t)gridDim.x * kDirectThreads, 0u, 0u, 0u);
   __syncthreads();
   tab.flush(a.t);
 }
@@ -526,7 +507,10 @@ __global__ void __launch_bounds__(kDirectThreads) gb_aggregate_kernel(Args a) {
 // and folds it partition by partition, flushing its LDS table at each
 // partition boundary (a partition's keys fit one table; the next partition's
 // keys are all different).  Equal shares keep every workgroup equally busy
-// whatever the partition sizes.
+// whatever the partition sizes.  Where a partition holds more keys than one
+// table (more partitions than the scatter takes), its rows are folded in
+// several passes, each taking the rows of one sub-partition (the next bits of
+// the key's hash) and flushing the table after it.
 template <int KD, int VD, int G>
 __global__ void __launch_bounds__(kPartThreads) gb_aggregate_part_kernel(Args a) {
   __shared__ LdsTable<G, lds_slots<G>(), kPartThreads> tab;
@@ -541,15 +525,20 @@ __global__ void __launch_bounds__(kPartThreads) gb_aggregate_part_kernel(Args a)
     else hi = mid - 1;
   }
   int p = lo;
+  const uint32_t sub_mask = (1u << a.pt.sub_bits) - 1u;
+  const uint32_t sub_shift = a.pt.sub_bits ? (uint32_t)(64 - a.pt.bits - a.pt.sub_bits) : 0u;
   while (r < r1) {
     while ((int64_t)a.pt.start[p + 1] <= r) ++p;  // skip partitions that end before r
     const int64_t seg_end = std::min<int64_t>(r1, (int64_t)a.pt.start[p + 1]);
-    tab.clear();
-    __syncthreads();
-    tab.template fold_rows<KD, VD>(a.t, a.pt.pk, a.pt.pv, r + threadIdx.x, seg_end, kPartThreads);
-    __syncthreads();
-    tab.flush(a.t);
-    __syncthreads();
+    for (uint32_t sub = 0; sub <= sub_mask; ++sub) {
+      tab.clear();
+      __syncthreads();
+      tab.template fold_rows<KD, VD>(a.t, a.pt.pk, a.pt.pv, r + threadIdx.x, seg_end, kPartThreads, sub_shift,
+                                     sub_mask, sub);
+      __syncthreads();
+      tab.flush(a.t);
+      __syncthreads();
+    }
     r = seg_end;
   }
 }
@@ -691,16 +680,9 @@ const void* agg_kernel(int32_t kd, int32_t vd, int g, bool part) {
 
 template <int KD>
 const void* scatter_kd(int32_t vd, bool hasv) {
-  if (!hasv) return reinterpret_cast<const void*>(&gb_scatter_kernel<KD, AGG_I32, false>);
-  if (vd == AGG_I64) return reinterpret_cast<const void*>(&gb_scatter_kernel<KD, AGG_I64, true>);
-  return reinterpret_cast<const void*>(&gb_scatter_kernel<KD, AGG_I32, true>);  // 4-byte values move as bits
-}
-
-template <int KD>
-const void* scatter_tiled_kd(int32_t vd, bool hasv) {
   if (!hasv) return reinterpret_cast<const void*>(&gb_scatter_tiled_kernel<KD, AGG_I32, false>);
   if (vd == AGG_I64) return reinterpret_cast<const void*>(&gb_scatter_tiled_kernel<KD, AGG_I64, true>);
-  return reinterpret_cast<const void*>(&gb_scatter_tiled_kernel<KD, AGG_I32, true>);
+  return reinterpret_cast<const void*>(&gb_scatter_tiled_kernel<KD, AGG_I32, true>);  // 4-byte values move as bits
 }
 
 const void* init_kernel(int g) {
@@ -789,6 +771,11 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
     bits = bits_for(lds_slots_of(g) / 2);
     bits = std::max(bits, kMinPartBits);  // few partitions would serialise the counting atomics
   }
+  // The scatter takes at most 2^kTileMaxBits partitions (its per-partition
+  // counters live in LDS, and more would shorten the coalesced runs); past
+  // that each partition is folded in 2^sub_bits passes.
+  const int sub_bits = std::max(0, bits - kTileMaxBits);
+  bits -= sub_bits;
   const int64_t P = bits ? (int64_t)1 << bits : 0;
   const int64_t crow = bits ? std::max<int64_t>(1, std::min<int64_t>(max_n, kChunkRows)) : 0;
   const int kw = width_of(key_dtype), vw = op == AGG_COUNT ? 0 : width_of(val_dtype);
@@ -825,6 +812,7 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   p->pt.pk = take(b_pk);
   p->pt.pv = vw ? take(b_pv) : nullptr;
   p->pt.bits = bits;
+  p->pt.sub_bits = sub_bits;
   p->device = dev;
   p->key_dtype = key_dtype;
   p->val_dtype = val_dtype;
@@ -887,11 +875,8 @@ int agg_groupby_run(agg_groupby_t p, const void* keys, const void* vals, int64_t
     const bool hasv = p->op != AGG_COUNT;
     const void* hist = p->key_dtype == AGG_I32 ? reinterpret_cast<const void*>(&gb_hist_kernel<AGG_I32>)
                                                : reinterpret_cast<const void*>(&gb_hist_kernel<AGG_I64>);
-    const bool tiled = p->pt.bits <= kTileMaxBits;
-    const void* scat = tiled ? (p->key_dtype == AGG_I32 ? scatter_tiled_kd<AGG_I32>(p->val_dtype, hasv)
-                                                        : scatter_tiled_kd<AGG_I64>(p->val_dtype, hasv))
-                             : (p->key_dtype == AGG_I32 ? scatter_kd<AGG_I32>(p->val_dtype, hasv)
-                                                        : scatter_kd<AGG_I64>(p->val_dtype, hasv));
+    const void* scat = p->key_dtype == AGG_I32 ? scatter_kd<AGG_I32>(p->val_dtype, hasv)
+                                               : scatter_kd<AGG_I64>(p->val_dtype, hasv);
     const void* aggk = agg_kernel(p->key_dtype, p->val_dtype, p->gop, true);
     for (int64_t c0 = 0; c0 < n; c0 += kChunkRows) {
       const int64_t m = std::min<int64_t>(kChunkRows, n - c0);
@@ -907,7 +892,7 @@ int agg_groupby_run(agg_groupby_t p, const void* keys, const void* vals, int64_t
       if ((rc = launch_lds(reinterpret_cast<const void*>(&gb_scan_tot_kernel), 1, kScanThreads, 0, &a, stream)) !=
           AGG_OK)
         return rc;
-      if ((rc = launch_lds(scat, a.pt.g1, tiled ? kTileThreads : kThreads, tiled ? 0 : lds, &a, stream)) != AGG_OK)
+      if ((rc = launch_lds(scat, a.pt.g1, kTileThreads, 0, &a, stream)) != AGG_OK)
         return rc;
       const int64_t agrid =
           std::max<int64_t>(1, std::min<int64_t>(ceil_div(m, kPartThreads * 8), (int64_t)cu * p->agg_blocks));

@@ -193,10 +193,14 @@ def test_groupby_partitioned_with_few_actual_groups(agg):
         vals = make_vals(n, vdt, seed=32)
         for op in ("sum", "min", "count"):
             run_case(agg, keys, vals, op, max_groups=100_000, ctx=f"few groups, big plan {vdt} {op}")
-    # more partitions than the tiled scatter takes: the row-by-row scatter
+    # more partitions than the scatter takes: several aggregation passes per partition
     many = make_keys(n, "i32", 20_000, seed=33)
     for vdt in ("f32", "i64"):
-        run_case(agg, many, make_vals(n, vdt, seed=34), "sum", max_groups=6_000_000, ctx=f"row scatter {vdt}")
+        for op in ("sum", "min", "count"):
+            run_case(agg, many, make_vals(n, vdt, seed=34), op, max_groups=6_000_000, ctx=f"sub-partitions {vdt} {op}")
+    wide = make_keys(n, "i64", 150_000, seed=35)      # 8 passes per partition for float sums
+    run_case(agg, wide, make_vals(n, "f32", seed=36), "sum", max_groups=8_000_000, ctx="8 sub-partitions f32 sum")
+    run_case(agg, wide, make_vals(n, "i32", seed=37), "avg", max_groups=30_000_000, ctx="8 sub-partitions i32 avg")
 
 
 def test_groupby_multi_chunk_closed_form(agg):
