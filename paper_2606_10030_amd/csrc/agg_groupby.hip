@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <limits>
 #include <new>
 #include <type_traits>
 
@@ -57,14 +58,18 @@ constexpr int tile_rows() { return (KD == AGG_I64 && VD == AGG_I64 && HASV) ? 40
 
 enum GOp { G_COUNT = 0, G_SUM_INT, G_MIN_INT, G_MAX_INT, G_SUM_F32, G_MIN_F32, G_MAX_F32 };
 
-// LDS tables: one 1024-thread workgroup per CU with a table of 4096 slots
-// (1024 for float sums, whose slots carry the digits), on both paths.
-// Measured against three 256-thread workgroups per CU with half the slots:
-// fewer, larger tables hold 2x the groups at the same load and fold faster.
+// LDS tables: one 1024-thread workgroup per CU with one table of up to
+// 128 KiB, on both paths: 8192 slots for 4-byte keys, 4096 for 8-byte keys
+// (twice that for COUNT, which keeps no value; 1024 for float sums, whose
+// slots carry the digits).  Measured against three 256-thread workgroups per
+// CU with half the slots: fewer, larger tables hold 2x the groups at the same
+// load and fold faster.
 constexpr int kDirectThreads = 1024;
-template <int G>
-constexpr int lds_slots() { return G == G_SUM_F32 ? 1024 : 4096; }
-inline int lds_slots_of(int g) { return g == G_SUM_F32 ? 1024 : 4096; }
+constexpr int lds_slots_of(int g, int kd) {
+  return g == G_SUM_F32 ? 1024 : (g == G_COUNT ? 2 : 1) * (kd == AGG_I32 ? 8192 : 4096);
+}
+template <int G, int KD>
+constexpr int lds_slots() { return lds_slots_of(G, KD); }
 constexpr int kPartThreads = 1024;
 
 struct Table {
@@ -393,21 +398,28 @@ __global__ void __launch_bounds__(kTileThreads) gb_scatter_tiled_kernel(Args a) 
 
 // ---- aggregation into LDS tables, flushed into the global table ----
 
-template <int G, int L_, int NT>
+// One workgroup's table: L hashed slots keyed in the key column's own width
+// (4-byte keys fit twice the slots of 8-byte ones), plus slot L for the one
+// key whose bit pattern marks an empty slot.
+template <int G, int KD, int L_, int NT>
 struct LdsTable {
+  using KT = typename std::conditional<KD == AGG_I32, int32_t, int64_t>::type;
+  using UKT = typename std::conditional<KD == AGG_I32, unsigned int, unsigned long long>::type;
+  static constexpr KT kMark = std::numeric_limits<KT>::min();  // empty hashed slot
   static constexpr int L = L_;
   static constexpr bool kDig = G == G_SUM_F32;
-  int64_t key[L];
-  uint32_t cnt[L];     // rows per table stay below 2^32 (a workgroup's share is at most 2^28 rows)
-  int64_t val[kDig ? 1 : L];
-  int64_t dig[kDig ? L * kDigits : 1];
-  int32_t flags[kDig ? L : 1];
+  static constexpr bool kVal = !kDig && G != G_COUNT;
+  KT key[L];
+  uint32_t cnt[L + 1];  // rows per table stay below 2^32 (a workgroup's share is at most 2^28 rows)
+  int64_t val[kVal ? L + 1 : 1];
+  int64_t dig[kDig ? (L + 1) * kDigits : 1];
+  int32_t flags[kDig ? L + 1 : 1];
 
   __device__ void clear() {
-    for (int e = threadIdx.x; e < L; e += NT) {
-      key[e] = kEmpty;
+    for (int e = threadIdx.x; e <= L; e += NT) {
+      if (e < L) key[e] = kMark;
       cnt[e] = 0;
-      if constexpr (!kDig) val[e] = val_identity<G>();
+      if constexpr (kVal) val[e] = val_identity<G>();
       if constexpr (kDig) {
         flags[e] = 0;
         for (int d = 0; d < kDigits; ++d) dig[e * kDigits + d] = 0;
@@ -418,7 +430,7 @@ struct LdsTable {
   // Rows first, first + step, ... below last whose key hash has the bits
   // (hash >> sub_shift) & sub_mask equal to sub; a row whose key finds no
   // slot within kLdsProbes goes to the global table.
-  template <int KD, int VD>
+  template <int VD>
   __device__ void fold_rows(const Table& t, const void* keys, const void* vals, int64_t first, int64_t last,
                             int64_t step, uint32_t sub_shift, uint32_t sub_mask, uint32_t sub) {
     constexpr int R = kAggRows;
@@ -441,40 +453,42 @@ struct LdsTable {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (base + r * step >= last) break;
-        const int64_t k = kk[r];
-        const uint64_t hk = mix64((uint64_t)k);
+        const KT k = (KT)kk[r];
+        const uint64_t hk = mix64((uint64_t)kk[r]);
         if (((uint32_t)(hk >> sub_shift) & sub_mask) != sub) continue;  // another pass's row
         int s = -1;
-        if (k != kEmpty) {
+        if (k == kMark) {
+          s = L;
+        } else {
           // double hashing: an odd step from the hash's high half, so probe
           // chains do not cluster (a wave waits for its longest chain)
           int h = (int)(hk & (L - 1));
           const int step = (int)(((hk >> 32) | 1) & (L - 1));
           for (int p = 0; p < kLdsProbes; ++p, h = (h + step) & (L - 1)) {
-            const int64_t cur = key[h];
+            const KT cur = key[h];
             if (cur == k) { s = h; break; }
-            if (cur == kEmpty) {
-              const int64_t prev = (int64_t)atomicCAS(reinterpret_cast<unsigned long long*>(&key[h]),
-                                                      (unsigned long long)kEmpty, (unsigned long long)k);
-              if (prev == kEmpty || prev == k) { s = h; break; }
+            if (cur == kMark) {
+              const KT prev = (KT)atomicCAS(reinterpret_cast<UKT*>(&key[h]), (UKT)kMark, (UKT)k);
+              if (prev == kMark || prev == k) { s = h; break; }
             }
           }
         }
         if (s >= 0) {
-          apply<G>(&cnt[s], kDig ? nullptr : &val[s], kDig ? &dig[s * kDigits] : nullptr,
+          apply<G>(&cnt[s], kVal ? &val[s] : nullptr, kDig ? &dig[s * kDigits] : nullptr,
                    kDig ? &flags[s] : nullptr, ivv[r], fvv[r]);
         } else {
-          { const int64_t g = global_slot(t, k); if (g >= 0) apply_global<G>(t, g, ivv[r], fvv[r]); }
+          const int64_t g = global_slot(t, kk[r]);
+          if (g >= 0) apply_global<G>(t, g, ivv[r], fvv[r]);
         }
       }
     }
   }
 
   __device__ void flush(const Table& t) {
-    for (int e = threadIdx.x; e < L; e += NT) {
-      const int64_t k = key[e];
-      if (k == kEmpty) continue;
-      const int64_t g = global_slot(t, k);
+    for (int e = threadIdx.x; e <= L; e += NT) {
+      const KT k = e < L ? key[e] : kMark;
+      if (e < L ? k == kMark : cnt[L] == 0) continue;
+      const int64_t g = global_slot(t, (int64_t)k);
       if (g < 0) continue;
       atomicAdd(reinterpret_cast<unsigned long long*>(t.cnt + g), (unsigned long long)cnt[e]);
       if constexpr (G == G_SUM_INT) atomicAdd(reinterpret_cast<unsigned long long*>(t.val + g), (unsigned long long)val[e]);
@@ -494,10 +508,10 @@ struct LdsTable {
 // Direct path: every workgroup sweeps the rows grid-stride into one LDS table.
 template <int KD, int VD, int G>
 __global__ void __launch_bounds__(kDirectThreads) gb_aggregate_kernel(Args a) {
-  __shared__ LdsTable<G, lds_slots<G>(), kDirectThreads> tab;
+  __shared__ LdsTable<G, KD, lds_slots<G, KD>(), kDirectThreads> tab;
   tab.clear();
   __syncthreads();
-  tab.template fold_rows<KD, VD>(a.t, a.keys, a.vals, (int64_t)blockIdx.x * kDirectThreads + threadIdx.x, a.n,
+  tab.template fold_rows<VD>(a.t, a.keys, a.vals, (int64_t)blockIdx.x * kDirectThreads + threadIdx.x, a.n,
                                  (int64_t)gridDim.x * kDirectThreads, 0u, 0u, 0u);
   __syncthreads();
   tab.flush(a.t);
@@ -513,7 +527,7 @@ __global__ void __launch_bounds__(kDirectThreads) gb_aggregate_kernel(Args a) {
 // the key's hash) and flushing the table after it.
 template <int KD, int VD, int G>
 __global__ void __launch_bounds__(kPartThreads) gb_aggregate_part_kernel(Args a) {
-  __shared__ LdsTable<G, lds_slots<G>(), kPartThreads> tab;
+  __shared__ LdsTable<G, KD, lds_slots<G, KD>(), kPartThreads> tab;
   const int P = 1 << a.pt.bits;
   int64_t r = a.n * (int64_t)blockIdx.x / gridDim.x;
   const int64_t r1 = a.n * ((int64_t)blockIdx.x + 1) / gridDim.x;
@@ -533,7 +547,7 @@ __global__ void __launch_bounds__(kPartThreads) gb_aggregate_part_kernel(Args a)
     for (uint32_t sub = 0; sub <= sub_mask; ++sub) {
       tab.clear();
       __syncthreads();
-      tab.template fold_rows<KD, VD>(a.t, a.pt.pk, a.pt.pv, r + threadIdx.x, seg_end, kPartThreads, sub_shift,
+      tab.template fold_rows<VD>(a.t, a.pt.pk, a.pt.pv, r + threadIdx.x, seg_end, kPartThreads, sub_shift,
                                      sub_mask, sub);
       __syncthreads();
       tab.flush(a.t);
@@ -762,13 +776,14 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   // quarter): the direct path up to half of its table, partitions sized for
   // half of theirs.
   int bits = 0;
-  if (max_groups > lds_slots_of(g) / 2) {
+  const int64_t half_table = lds_slots_of(g, key_dtype) / 2;
+  if (max_groups > half_table) {
     auto bits_for = [max_groups](int64_t per_part) {
       int b = 0;
       while (b < kMaxPartBits && (per_part << b) < max_groups) ++b;
       return b;
     };
-    bits = bits_for(lds_slots_of(g) / 2);
+    bits = bits_for(half_table);
     bits = std::max(bits, kMinPartBits);  // few partitions would serialise the counting atomics
   }
   // The scatter takes at most 2^kTileMaxBits partitions (its per-partition

@@ -203,6 +203,20 @@ def test_groupby_partitioned_with_few_actual_groups(agg):
     run_case(agg, wide, make_vals(n, "i32", seed=37), "avg", max_groups=30_000_000, ctx="8 sub-partitions i32 avg")
 
 
+@pytest.mark.parametrize("kdt,vdt,op,half", [
+    ("i32", "i64", "sum", 4096), ("i32", "i32", "count", 8192), ("i32", "f32", "sum", 512),
+    ("i64", "i64", "max", 2048), ("i64", "i32", "count", 4096), ("i64", "f32", "avg", 512)])
+def test_groupby_path_boundaries(agg, kdt, vdt, op, half):
+    """Plans at half an LDS table (the last direct plan) and one group past it
+    (the first partitioned plan), each with exactly max_groups distinct keys."""
+    n = 300_007
+    for groups in (half, half + 1):
+        keys = make_keys(n, kdt, groups, seed=groups)
+        assert np.unique(keys).size == groups
+        vals = make_vals(n, vdt, seed=groups + 7)
+        run_case(agg, keys, vals, op, max_groups=groups, ctx=f"{kdt}/{vdt} {op} {groups} groups")
+
+
 def test_groupby_multi_chunk_closed_form(agg):
     """More rows than one partitioning chunk (2^26): per-key sums with closed forms."""
     import torch
