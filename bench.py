@@ -291,7 +291,7 @@ def bench_groupby(agg, torch, stream, dev):
     cardinality) with int64 or float32 values.  Bytes = keys + values read once."""
     n = 1 << 28
     out = {}
-    for card in (16, 1024, 1 << 16, 1 << 20):
+    for card in (16, 1024, 8192, 1 << 16, 1 << 20):
         keys = torch.remainder(dev["i32"][:n].to(torch.int64) * 2654435761, card).to(torch.int32)
         for vdt, op in (("i64", "sum"), ("f32", "sum"), ("i32", "count")):
             g = agg.GroupBy("i32", vdt, op, max_n=n, max_groups=card)

@@ -267,8 +267,8 @@ typedef struct agg_groupby_s* agg_groupby_t;
  * with up to max_n items and max_groups distinct keys: allocates the device
  * hash table (2 x max_groups slots rounded up to a power of two; float SUM /
  * AVG tables carry 9 fixed-point digits per slot); with more groups than a
- * workgroup's LDS table holds, also a staging copy of up to 2^26 rows and a
- * partition histogram.  max_n <= 2^36; float SUM / AVG plans take at most
+ * workgroup's LDS table holds, also a staging copy of min(max_n, 2^28) rows
+ * and a partition histogram.  max_n <= 2^36; float SUM / AVG plans take at most
  * 2^31 items per run. */
 int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, int32_t op, int64_t max_n,
                      int64_t max_groups);

@@ -46,9 +46,12 @@ constexpr int kLdsProbes = 16;
 constexpr int kAggRows = 8;           // rows whose loads a thread keeps in flight
 constexpr int kMaxPartBits = 14;      // at most 16384 (sub-)partitions
 constexpr int kMinPartBits = 5;       // at least 32
-constexpr int64_t kChunkRows = (int64_t)1 << 26;
-constexpr int64_t kHistRows = (int64_t)1 << 16;    // rows per histogram / scatter workgroup
-constexpr int kMaxHistWg = (int)(kChunkRows / kHistRows);
+// Rows are partitioned in chunks of up to 2^28: every chunk ends with each
+// aggregation workgroup flushing the groups it holds, so fewer, larger
+// chunks flush less (the staging area holds one chunk: up to 4 GiB).
+constexpr int64_t kChunkRows = (int64_t)1 << 28;
+constexpr int kMaxHistWg = 1024;                   // histogram / scatter workgroups per chunk
+constexpr int64_t kMinHistRows = 8192;             // rows per such workgroup, at least
 constexpr int kScanThreads = 1024;
 constexpr int kTileThreads = 1024;    // scatter: rows staged in LDS per tile
 constexpr int kTileMaxBits = 11;      // scatter into at most 2048 partitions
@@ -87,7 +90,7 @@ struct Part {
   uint32_t* hist;      // [P][g1]: rows of partition p in scatter workgroup g, then their prefix
   uint32_t* tot;       // [P] rows per partition
   uint32_t* start;     // [P + 1] first staged row of each partition
-  void* pk;            // staged keys (kChunkRows)
+  void* pk;            // staged keys (one chunk)
   void* pv;            // staged values (none for COUNT)
   int32_t bits;        // log2 of the number of partitions the rows are scattered into
   int32_t sub_bits;    // log2 of the aggregation passes over each of them (one per sub-partition)
@@ -910,7 +913,7 @@ int agg_groupby_run(agg_groupby_t p, const void* keys, const void* vals, int64_t
       a.keys = static_cast<const char*>(keys) + c0 * kw;
       a.vals = static_cast<const char*>(vals) + c0 * vw;
       a.n = m;
-      a.pt.g1 = (int)std::min<int64_t>(kMaxHistWg, ceil_div(m, kHistRows));
+      a.pt.g1 = (int)std::min<int64_t>(kMaxHistWg, ceil_div(m, kMinHistRows));
       a.pt.rows_per_wg = ceil_div(m, a.pt.g1);
       if ((rc = launch_lds(hist, a.pt.g1, kThreads, lds, &a, stream)) != AGG_OK) return rc;
       if ((rc = launch_lds(reinterpret_cast<const void*>(&gb_scan_rows_kernel), ceil_div(P, kThreads / 64), kThreads,

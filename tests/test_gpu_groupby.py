@@ -220,24 +220,29 @@ def test_groupby_path_boundaries(agg, kdt, vdt, op, half):
 
 
 def test_groupby_multi_chunk_closed_form(agg):
-    """More rows than one partitioning chunk (2^26): per-key sums with closed forms."""
+    """More rows than one partitioning chunk (2^28), more groups than the
+    direct path takes: per-key sums with closed forms."""
+    import math
     import torch
-    n = (1 << 26) + 4099
-    card = 3001
+    n = (1 << 28) + 4099
+    card = 10007
     idx = torch.arange(n, dtype=torch.int64, device="cuda")
     keys = (idx % card).to(torch.int32)
-    cnt = np.bincount(np.arange(n, dtype=np.int64) % card, minlength=card)
-    got = agg.GroupBy("i32", "i64", "sum", max_n=n, max_groups=card).run(keys, idx)
     r = np.arange(card, dtype=np.int64)
+    cnt = n // card + (r < n % card)                          # rows r, r + card, r + 2 card, ...
+    got = agg.GroupBy("i32", "i64", "sum", max_n=n, max_groups=card).run(keys, idx)
     want_sum = r * cnt + card * cnt * (cnt - 1) // 2          # sum of r + card*j for j < cnt[r]
     assert [g[0] for g in got] == list(range(card))
     assert [g[3] for g in got] == cnt.tolist()
     assert [g[1] for g in got] == want_sum.tolist()
     vf = ((idx % 7) - 3).to(torch.float32)
+    del idx
     got = agg.GroupBy("i32", "f32", "sum", max_n=n, max_groups=card).run(keys, vf)
-    i = np.arange(n, dtype=np.int64)
-    want_f = np.bincount(i % card, weights=((i % 7) - 3).astype(np.float64), minlength=card)
-    assert [g[2] for g in got] == want_f.tolist()
+    # (r + card*j) mod 7 runs through all residues every 7 steps of j (card is
+    # prime to 7) and those 7 values of x - 3 sum to 0: only the last cnt mod 7 count
+    assert math.gcd(card, 7) == 1
+    want_f = [float(sum((rr + card * j) % 7 - 3 for j in range(c % 7))) for rr, c in zip(r.tolist(), cnt.tolist())]
+    assert [g[2] for g in got] == want_f
 
 
 def test_groupby_float_sum_rounding_cases(agg):
