@@ -208,9 +208,9 @@ def test_groupby_partitioned_with_few_actual_groups(agg):
     ("i64", "i64", "max", 2048), ("i64", "i32", "count", 4096), ("i64", "f32", "avg", 512)])
 def test_groupby_path_boundaries(agg, kdt, vdt, op, half):
     """Plans at half an LDS table (the last one-pass direct plan), one group
-    past it (two direct passes), at a whole table (the last two-pass plan)
-    and one past that (the first partitioned plan), each with exactly
-    max_groups distinct keys."""
+    past it (two direct passes; COUNT: partitioned), at a whole table (the
+    last two-pass plan) and one past that (the first partitioned plan), each
+    with exactly max_groups distinct keys."""
     n = 300_007
     for groups in (half, half + 1, 2 * half, 2 * half + 1):
         keys = make_keys(n, kdt, groups, seed=groups)
