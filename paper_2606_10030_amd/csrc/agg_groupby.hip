@@ -11,14 +11,17 @@
 // per (workgroup, key) instead of one per row.
 //
 // Two paths, chosen from the plan's max_groups:
-//  * direct: every workgroup's LDS table holds all the groups in at most half
-//    of its slots; workgroups stride over the rows.
-//  * partitioned (more groups than an LDS table holds): rows are processed in
-//    chunks; each chunk is radix-partitioned on the top bits of the key's
-//    hash (histogram, prefix sums, scatter into a staging copy), so that one
-//    partition has few enough distinct keys for an LDS table, and then one
-//    workgroup (or several, for a partition with many rows) aggregates each
-//    partition in LDS.
+//  * direct: workgroups stride over the rows; every workgroup's LDS table
+//    holds all the groups in at most half of its slots (or, with up to twice
+//    that many, in two passes over the rows, each taking the keys of one half
+//    of the hash space).
+//  * partitioned (more groups): rows are processed in chunks; each chunk is
+//    radix-partitioned on the top bits of the key's hash (histogram, prefix
+//    sums, scatter into a staging copy), so that one partition has few enough
+//    distinct keys for an LDS table, and then one workgroup (or several, for
+//    a partition with many rows) aggregates each partition in LDS (in several
+//    passes, one per sub-partition, where the scatter's partitions are too
+//    few for that).
 //
 // Determinism: integer SUM (mod 2^64), MIN, MAX and COUNT are exact in any
 // order.  A float32 SUM is accumulated exactly: every finite float is
@@ -218,14 +221,6 @@ __device__ __forceinline__ int64_t global_slot(const Table& t, int64_t k) {
 template <int G>
 __device__ __forceinline__ void apply_global(const Table& t, int64_t s, int64_t iv, float fv) {
   apply<G>(t.cnt + s, t.val + s, t.dig + (G == G_SUM_F32 ? s * kDigits : 0), t.flags + s, iv, fv);
-}
-
-// A row whose key found no LDS slot: straight into the global table.  Rare,
-// so kept out of line to keep the hot loop small.
-template <int G>
-__device__ __attribute__((noinline)) void spill_row(Table t, int64_t k, int64_t iv, float fv) {
-  const int64_t g = global_slot(t, k);
-  if (g >= 0) apply_global<G>(t, g, iv, fv);
 }
 
 // ---- histogram / prefix sums / scatter of the partitioned path ----
