@@ -53,7 +53,8 @@ def kernel_source_hash() -> str:
 
 def traffic_for(kernel: str, n_bytes_alg: int):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel sources; else None."""
+    taken on the current kernel sources and on a launch of the same
+    algorithmic size; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
@@ -62,7 +63,9 @@ def traffic_for(kernel: str, n_bytes_alg: int):
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
     k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("hbm_bytes_per_launch")
+    if k is None or k.get("algorithmic_bytes") != n_bytes_alg:
+        return None
+    return k.get("hbm_bytes_per_launch")
 
 
 def counters_mode(n: int):
