@@ -170,29 +170,65 @@ __device__ __forceinline__ int64_t load_ival(const void* p, int64_t i) {
   else return static_cast<const int64_t*>(p)[i];
 }
 
-// Fold one row into a slot (LDS or global: the pointers decide).
-template <int G, typename CT>
+// Atomics on a slot of an LDS table (workgroup scope) or of the global
+// table (device scope).  The LDS forms name the LDS address space: left to
+// infer it, the compiler may merge a row's LDS update with the global one of
+// the fallback path into a single generic (flat) atomic, which is far slower
+// on LDS than a DS atomic.
+typedef __attribute__((address_space(3))) unsigned int lds_u32;
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+typedef __attribute__((address_space(3))) long long lds_i64;
+typedef __attribute__((address_space(3))) int lds_i32;
+
+template <bool LDS>
+__device__ __forceinline__ void at_add(unsigned int* p, unsigned int v) {
+  if constexpr (LDS) __hip_atomic_fetch_add((lds_u32*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else atomicAdd(p, v);
+}
+template <bool LDS>
+__device__ __forceinline__ void at_add(unsigned long long* p, unsigned long long v) {
+  if constexpr (LDS) __hip_atomic_fetch_add((lds_u64*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else atomicAdd(p, v);
+}
+template <bool LDS>
+__device__ __forceinline__ void at_min(long long* p, long long v) {
+  if constexpr (LDS) __hip_atomic_fetch_min((lds_i64*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else atomicMin(p, v);
+}
+template <bool LDS>
+__device__ __forceinline__ void at_max(long long* p, long long v) {
+  if constexpr (LDS) __hip_atomic_fetch_max((lds_i64*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else atomicMax(p, v);
+}
+template <bool LDS>
+__device__ __forceinline__ void at_or(int* p, int v) {
+  if constexpr (LDS) __hip_atomic_fetch_or((lds_i32*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else atomicOr(p, v);
+}
+
+// Fold one row into a slot of an LDS table (LDS) or of the global table.
+template <int G, bool LDS, typename CT>
 __device__ __forceinline__ void apply(CT* cnt, int64_t* val, int64_t* dig, int32_t* flags, int64_t iv, float fv) {
-  if constexpr (sizeof(CT) == 8) atomicAdd(reinterpret_cast<unsigned long long*>(cnt), 1ull);
-  else atomicAdd(reinterpret_cast<unsigned int*>(cnt), 1u);
-  if constexpr (G == G_SUM_INT) atomicAdd(reinterpret_cast<unsigned long long*>(val), (unsigned long long)iv);
-  if constexpr (G == G_MIN_INT) atomicMin(reinterpret_cast<long long*>(val), (long long)iv);
-  if constexpr (G == G_MAX_INT) atomicMax(reinterpret_cast<long long*>(val), (long long)iv);
+  if constexpr (sizeof(CT) == 8) at_add<LDS>(reinterpret_cast<unsigned long long*>(cnt), 1ull);
+  else at_add<LDS>(reinterpret_cast<unsigned int*>(cnt), 1u);
+  if constexpr (G == G_SUM_INT) at_add<LDS>(reinterpret_cast<unsigned long long*>(val), (unsigned long long)iv);
+  if constexpr (G == G_MIN_INT) at_min<LDS>(reinterpret_cast<long long*>(val), (long long)iv);
+  if constexpr (G == G_MAX_INT) at_max<LDS>(reinterpret_cast<long long*>(val), (long long)iv);
   if constexpr (G == G_MIN_F32 || G == G_MAX_F32) {
     if (!__builtin_isnan(fv)) {
-      if constexpr (G == G_MIN_F32) atomicMin(reinterpret_cast<long long*>(val), (long long)f32_order(fv));
-      else atomicMax(reinterpret_cast<long long*>(val), (long long)f32_order(fv));
+      if constexpr (G == G_MIN_F32) at_min<LDS>(reinterpret_cast<long long*>(val), (long long)f32_order(fv));
+      else at_max<LDS>(reinterpret_cast<long long*>(val), (long long)f32_order(fv));
     }
   }
   if constexpr (G == G_SUM_F32) {
     if (!__builtin_isfinite(fv)) {
-      atomicOr(flags, __builtin_isnan(fv) ? 1 : (fv > 0 ? 2 : 4));
+      at_or<LDS>(flags, __builtin_isnan(fv) ? 1 : (fv > 0 ? 2 : 4));
     } else {
       int k;
       int64_t lo, hi;
       f32_digits(fv, &k, &lo, &hi);
-      if (lo) atomicAdd(reinterpret_cast<unsigned long long*>(dig + k), (unsigned long long)lo);
-      if (hi) atomicAdd(reinterpret_cast<unsigned long long*>(dig + k + 1), (unsigned long long)hi);
+      if (lo) at_add<LDS>(reinterpret_cast<unsigned long long*>(dig + k), (unsigned long long)lo);
+      if (hi) at_add<LDS>(reinterpret_cast<unsigned long long*>(dig + k + 1), (unsigned long long)hi);
     }
   }
 }
@@ -220,7 +256,7 @@ __device__ __forceinline__ int64_t global_slot(const Table& t, int64_t k) {
 
 template <int G>
 __device__ __forceinline__ void apply_global(const Table& t, int64_t s, int64_t iv, float fv) {
-  apply<G>(t.cnt + s, t.val + s, t.dig + (G == G_SUM_F32 ? s * kDigits : 0), t.flags + s, iv, fv);
+  apply<G, false>(t.cnt + s, t.val + s, t.dig + (G == G_SUM_F32 ? s * kDigits : 0), t.flags + s, iv, fv);
 }
 
 // ---- histogram / prefix sums / scatter of the partitioned path ----
@@ -472,8 +508,8 @@ struct LdsTable {
           }
         }
         if (s >= 0) {
-          apply<G>(&cnt[s], kVal ? &val[s] : nullptr, kDig ? &dig[s * kDigits] : nullptr,
-                   kDig ? &flags[s] : nullptr, ivv[r], fvv[r]);
+          apply<G, true>(&cnt[s], &val[kVal ? s : 0], &dig[kDig ? s * kDigits : 0], &flags[kDig ? s : 0], ivv[r],
+                         fvv[r]);
         } else {
           const int64_t g = global_slot(t, kk[r]);
           if (g >= 0) apply_global<G>(t, g, ivv[r], fvv[r]);

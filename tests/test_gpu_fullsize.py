@@ -134,3 +134,52 @@ def test_paper_shaped_key_column(agg):
     check(x, "i32", "sum", "neumaier", got, ctx="paper-shaped SF200")
     del d, h
     free()
+
+
+@pytest.mark.parametrize("card", [16, 8192, 1 << 20])
+def test_groupby_full_size(agg, card):
+    """Group-by as the benchmark runs it: 2^28 rows, int32 keys
+    (2654435761 x) mod card of the uniform int32 column x, uniform int64 /
+    float32 values, default plans for max_groups = card.  Every group's key
+    and count against a host count of the keys; sampled groups' SUM / AVG /
+    COUNT against the oracle over exactly that group's rows; the int64 group
+    sums add up (mod 2^64) to the oracle's sum of the whole value column."""
+    import torch
+    n = 1 << 28
+    t0 = time.time()
+    xh = pinned_column(n, "i32", "uniform", 2)
+    keys_d = torch.remainder(xh.to("cuda").to(torch.int64) * 2654435761, card).to(torch.int32)
+    keys = keys_d.cpu().numpy()
+    cnt = np.bincount(keys, minlength=card)
+    present = np.flatnonzero(cnt)
+    rng = np.random.default_rng(card)
+    pick = rng.choice(present, size=min(22, present.size), replace=False)
+    sample = np.unique(np.concatenate([present[[0, -1]], pick]))
+    rows = {int(k): np.flatnonzero(keys == k) for k in sample}
+    say(f"group-by {card} keys: inputs and {sample.size} sampled groups in {time.time() - t0:.1f}s")
+    for vdt, op, seed in (("i64", "sum", 3), ("f32", "sum", 4), ("f32", "avg", 4), ("i32", "count", 2)):
+        vh = xh if vdt == "i32" else pinned_column(n, vdt, "uniform", seed)
+        v = vh.numpy()
+        vd = vh.to("cuda")
+        got = agg.GroupBy("i32", vdt, op, max_n=n, max_groups=card).run(keys_d, vd)
+        ctx = f"group-by {card} keys {op}({vdt})"
+        assert got is not None, f"{ctx}: reported overflow"
+        assert [g[0] for g in got] == present.tolist(), ctx
+        assert [g[3] for g in got] == cnt[present].tolist(), ctx
+        by_key = {g[0]: g for g in got}
+        for k, idx in rows.items():
+            ref = oracle.aggregate(v[idx], op)
+            g = by_key[k]
+            if vdt == "f32":
+                assert g[2] == ref.f64, f"{ctx}: key {k} {g[2]!r} != {ref.f64!r}"
+            else:
+                assert g[1] == ref.i64, f"{ctx}: key {k} {g[1]} != {ref.i64}"
+        if vdt == "i64":
+            total = sum(g[1] for g in got) % 2**64
+            want = oracle.aggregate(v, "sum").i64 % 2**64
+            assert total == want, f"{ctx}: group sums add to {total}, column sum {want}"
+        del vd
+        free()
+        say(f"  {op}({vdt}): {len(got)} groups checked at {time.time() - t0:.1f}s")
+    del keys_d
+    free()

@@ -219,6 +219,27 @@ def test_groupby_path_boundaries(agg, kdt, vdt, op, half):
         run_case(agg, keys, vals, op, max_groups=groups, ctx=f"{kdt}/{vdt} {op} {groups} groups")
 
 
+def test_groupby_result_independent_of_path(agg):
+    """The same rows through every path -- one direct pass, two direct passes,
+    partitioned, partitioned with sub-partition passes -- give the same groups
+    bit for bit (float sums are exact, so no path's row order shows)."""
+    import torch
+    n = 400_009
+    keys = make_keys(n, "i32", 300, seed=41)
+    dk = torch.from_numpy(keys).to("cuda")
+    for vdt, op in (("f32", "sum"), ("f32", "avg"), ("i64", "sum"), ("f32", "max")):
+        vals = make_vals(n, vdt, seed=42)
+        dv = torch.from_numpy(vals).to("cuda")
+        want = oracle.groupby(keys, vals, op)
+        first = None
+        for mg in (300, 600, 5000, 100_000, 6_000_000):
+            got = agg.GroupBy("i32", vdt, op, max_n=n, max_groups=mg).run(dk, dv)
+            compare(got, want, f"{vdt} {op} max_groups={mg}")
+            if first is None:
+                first = got
+            assert got == first, f"{vdt} {op}: max_groups={mg} differs from max_groups=300"
+
+
 def test_groupby_multi_chunk_closed_form(agg):
     """More rows than one partitioning chunk (2^28), more groups than the
     direct path takes: per-key sums with closed forms."""
