@@ -27,10 +27,19 @@ constexpr int kCombineLanes = 256;              // lanes of the canonical final 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------ loads
+// Columns live in global memory (device memory, or pinned host memory mapped
+// into the device's address space), and the loads say so: a column address
+// the compiler cannot trace to a kernel argument (one read from a batch work
+// record) would otherwise get flat loads.
+typedef __attribute__((address_space(1))) const u32x4 global_u32x4;
+typedef __attribute__((address_space(1))) const uint32_t global_u32;
+typedef __attribute__((address_space(1))) const uint64_t global_u64;
+
 template <bool NT>
 __device__ __forceinline__ u32x4 load_vec_aligned(const char* p) {
-  if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
-  else return *reinterpret_cast<const u32x4*>(p);
+  global_u32x4* q = (global_u32x4*)p;
+  if constexpr (NT) return __builtin_nontemporal_load(q);
+  else return *q;
 }
 
 // 16 bytes at an address aligned only to the item width W (4 or 8).
@@ -38,14 +47,20 @@ template <bool NT, int W>
 __device__ __forceinline__ u32x4 load_vec_unaligned(const char* p) {
   u32x4 v;
   if constexpr (W == 4) {
-    const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+    global_u32* q = (global_u32*)p;
     v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
   } else {
-    const uint64_t* q = reinterpret_cast<const uint64_t*>(p);
+    global_u64* q = (global_u64*)p;
     uint64_t a = q[0], b = q[1];
     v[0] = (uint32_t)a; v[1] = (uint32_t)(a >> 32); v[2] = (uint32_t)b; v[3] = (uint32_t)(b >> 32);
   }
   return v;
+}
+
+// One item of type T (ragged tails).
+template <typename T>
+__device__ __forceinline__ T load_item(const char* p) {
+  return *(__attribute__((address_space(1))) const T*)p;
 }
 
 template <bool NT, bool AL, int W>
@@ -74,7 +89,7 @@ template <> struct Fold<K_SUM_I32> {
   static constexpr int W = 4, V = 4;
   using acc = uint64_t; using part = uint64_t;
   static __device__ acc identity() { return 0; }
-  static __device__ void add_item(acc& a, const char* p) { a += (uint64_t)(int64_t)*(const int32_t*)p; }
+  static __device__ void add_item(acc& a, const char* p) { a += (uint64_t)(int64_t)load_item<int32_t>(p); }
   static __device__ void add_vec(acc* a, u32x4 x) {
     for (int k = 0; k < 4; ++k) a[k] += (uint64_t)(int64_t)as_i32(x[k]);
   }
@@ -88,7 +103,7 @@ template <> struct Fold<K_SUM_I64> {
   static constexpr int W = 8, V = 2;
   using acc = uint64_t; using part = uint64_t;
   static __device__ acc identity() { return 0; }
-  static __device__ void add_item(acc& a, const char* p) { a += *(const uint64_t*)p; }
+  static __device__ void add_item(acc& a, const char* p) { a += load_item<uint64_t>(p); }
   static __device__ void add_vec(acc* a, u32x4 x) { a[0] += as_u64(x[0], x[1]); a[1] += as_u64(x[2], x[3]); }
   static __device__ acc merge(acc a, acc b) { return a + b; }
   static __device__ part to_part(acc a) { return a; }
@@ -101,7 +116,7 @@ template <bool IS_MIN> struct FoldMinMaxI32 {
   using acc = int32_t; using part = int64_t;
   static __device__ acc identity() { return IS_MIN ? INT32_MAX : INT32_MIN; }
   static __device__ acc merge(acc a, acc b) { return IS_MIN ? min(a, b) : max(a, b); }
-  static __device__ void add_item(acc& a, const char* p) { a = merge(a, *(const int32_t*)p); }
+  static __device__ void add_item(acc& a, const char* p) { a = merge(a, load_item<int32_t>(p)); }
   static __device__ void add_vec(acc* a, u32x4 x) { for (int k = 0; k < 4; ++k) a[k] = merge(a[k], as_i32(x[k])); }
   static __device__ part to_part(acc a) { return (int64_t)a; }
   static __device__ part pidentity() { return IS_MIN ? INT64_MAX : INT64_MIN; }
@@ -115,7 +130,7 @@ template <bool IS_MIN> struct FoldMinMaxI64 {
   using acc = int64_t; using part = int64_t;
   static __device__ acc identity() { return IS_MIN ? INT64_MAX : INT64_MIN; }
   static __device__ acc merge(acc a, acc b) { return IS_MIN ? min(a, b) : max(a, b); }
-  static __device__ void add_item(acc& a, const char* p) { a = merge(a, *(const int64_t*)p); }
+  static __device__ void add_item(acc& a, const char* p) { a = merge(a, load_item<int64_t>(p)); }
   static __device__ void add_vec(acc* a, u32x4 x) {
     a[0] = merge(a[0], (int64_t)as_u64(x[0], x[1]));
     a[1] = merge(a[1], (int64_t)as_u64(x[2], x[3]));
@@ -134,7 +149,7 @@ template <bool WIDE> struct FoldSumF32 {
   using acc = float;
   using part = typename std::conditional<WIDE, double, float>::type;
   static __device__ acc identity() { return 0.0f; }
-  static __device__ void add_item(acc& a, const char* p) { a += *(const float*)p; }
+  static __device__ void add_item(acc& a, const char* p) { a += load_item<float>(p); }
   static __device__ void add_vec(acc* a, u32x4 x) { for (int k = 0; k < 4; ++k) a[k] += as_f32(x[k]); }
   static __device__ acc merge(acc a, acc b) { return a + b; }
   static __device__ part to_part(acc a) { return (part)a; }
@@ -160,7 +175,7 @@ template <> struct Fold<K_SUM_F32_NEU> {
     a.c += (big - t) + small;
     a.s = t;
   }
-  static __device__ void add_item(acc& a, const char* p) { add(a, *(const float*)p); }
+  static __device__ void add_item(acc& a, const char* p) { add(a, load_item<float>(p)); }
   static __device__ void add_vec(acc* a, u32x4 x) { for (int k = 0; k < 4; ++k) add(a[k], as_f32(x[k])); }
   // Two pairs: Knuth's two-sum gives the exact error e of s1 + s2 (unique,
   // hence symmetric in the operands), which joins the corrections.
@@ -181,7 +196,7 @@ template <bool IS_MIN> struct FoldMinMaxF32 {
   // fminf / fmaxf: IEEE minNum / maxNum, a NaN operand yields the other one.
   static __device__ acc identity() { return __builtin_nanf(""); }
   static __device__ acc merge(acc a, acc b) { return IS_MIN ? fminf(a, b) : fmaxf(a, b); }
-  static __device__ void add_item(acc& a, const char* p) { a = merge(a, *(const float*)p); }
+  static __device__ void add_item(acc& a, const char* p) { a = merge(a, load_item<float>(p)); }
   static __device__ void add_vec(acc* a, u32x4 x) { for (int k = 0; k < 4; ++k) a[k] = merge(a[k], as_f32(x[k])); }
   static __device__ part to_part(acc a) { return a; }
   static __device__ part pidentity() { return identity(); }
