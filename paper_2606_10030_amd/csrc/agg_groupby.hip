@@ -65,15 +65,22 @@ constexpr int tile_rows() { return (KD == AGG_I64 && VD == AGG_I64 && HASV) ? 40
 enum GOp { G_COUNT = 0, G_SUM_INT, G_MIN_INT, G_MAX_INT, G_SUM_F32, G_MIN_F32, G_MAX_F32 };
 
 // LDS tables: one 1024-thread workgroup per CU with one table of up to
-// 128 KiB, on both paths: 8192 slots for 4-byte keys, 4096 for 8-byte keys
-// (twice that for COUNT, which keeps no value; 1024 for float sums, whose
-// slots carry the digits).  Measured against three 256-thread workgroups per
+// 148 KiB, on both paths: 8192 slots for 4-byte keys, 4096 for 8-byte keys
+// (twice that for COUNT, which keeps no value; 2048 for float sums, whose
+// slots carry 7 fixed-point digits).  Measured against three 256-thread workgroups per
 // CU with half the slots: fewer, larger tables hold 2x the groups at the same
 // load and fold faster.
 constexpr int kDirectThreads = 1024;
 constexpr int lds_slots_of(int g, int kd) {
-  return g == G_SUM_F32 ? 1024 : (g == G_COUNT ? 2 : 1) * (kd == AGG_I32 ? 8192 : 4096);
+  return g == G_SUM_F32 ? 2048 : (g == G_COUNT ? 2 : 1) * (kd == AGG_I32 ? 8192 : 4096);
 }
+// A float sum's LDS slot keeps digits 1..7 of the 9: a finite float
+// m * 2^(k-149) touches digits k/32 and k/32 + 1, both within 1..7 for
+// 32 <= k <= 223 (2^-94 <= |x| < 2^98: normal floats of biased exponent
+// 33..224).  Zeros add nothing and non-finite floats only set flags; every
+// other float is folded straight into the global table.  Seven digits
+// instead of nine fit twice the slots in LDS.
+constexpr int kLdsDigits = 7;
 template <int G, int KD>
 constexpr int lds_slots() { return lds_slots_of(G, KD); }
 constexpr int kPartThreads = 1024;
@@ -168,6 +175,13 @@ template <int VD>
 __device__ __forceinline__ int64_t load_ival(const void* p, int64_t i) {
   if constexpr (VD == AGG_I32) return (int64_t) static_cast<const int32_t*>(p)[i];
   else return static_cast<const int64_t*>(p)[i];
+}
+
+// Whether an LDS float-sum slot (digits 1..7) can take x.
+__device__ __forceinline__ bool lds_digits_hold(float x) {
+  const uint32_t b = __float_as_uint(x);
+  const uint32_t e = (b >> 23) & 0xFFu;
+  return (e - 33u) <= 191u || (b << 1) == 0u || e == 0xFFu;
 }
 
 // Atomics on a slot of an LDS table (workgroup scope) or of the global
@@ -446,7 +460,7 @@ struct LdsTable {
   KT key[L];
   uint32_t cnt[L + 1];  // rows per table stay below 2^32 (a workgroup's share is at most 2^28 rows)
   int64_t val[kVal ? L + 1 : 1];
-  int64_t dig[kDig ? (L + 1) * kDigits : 1];
+  int64_t dig[kDig ? (L + 1) * kLdsDigits : 1];  // digits 1..7 of a float sum
   int32_t flags[kDig ? L + 1 : 1];
 
   __device__ void clear() {
@@ -456,7 +470,7 @@ struct LdsTable {
       if constexpr (kVal) val[e] = val_identity<G>();
       if constexpr (kDig) {
         flags[e] = 0;
-        for (int d = 0; d < kDigits; ++d) dig[e * kDigits + d] = 0;
+        for (int d = 0; d < kLdsDigits; ++d) dig[e * kLdsDigits + d] = 0;
       }
     }
   }
@@ -490,8 +504,12 @@ struct LdsTable {
         const KT k = (KT)kk[r];
         const uint64_t hk = mix64((uint64_t)kk[r]);
         if (((uint32_t)(hk >> sub_shift) & sub_mask) != sub) continue;  // another pass's row
+        bool in_lds = true;
+        if constexpr (kDig) in_lds = lds_digits_hold(fvv[r]);
         int s = -1;
-        if (k == kMark) {
+        if (!in_lds) {
+          // digit 0 or 8: the global table below
+        } else if (k == kMark) {
           s = L;
         } else {
           // double hashing: an odd step from the hash's high half, so probe
@@ -508,8 +526,22 @@ struct LdsTable {
           }
         }
         if (s >= 0) {
-          apply<G, true>(&cnt[s], &val[kVal ? s : 0], &dig[kDig ? s * kDigits : 0], &flags[kDig ? s : 0], ivv[r],
-                         fvv[r]);
+          if constexpr (kDig) {
+            at_add<true>(&cnt[s], 1u);
+            if (!__builtin_isfinite(fvv[r])) {
+              at_or<true>(&flags[s], __builtin_isnan(fvv[r]) ? 1 : (fvv[r] > 0 ? 2 : 4));
+            } else {  // digit j of the sum sits at dig[s * kLdsDigits + j - 1]
+              int dk;
+              int64_t dlo, dhi;
+              f32_digits(fvv[r], &dk, &dlo, &dhi);
+              if (dlo) at_add<true>(reinterpret_cast<unsigned long long*>(&dig[s * kLdsDigits + dk - 1]),
+                                    (unsigned long long)dlo);
+              if (dhi) at_add<true>(reinterpret_cast<unsigned long long*>(&dig[s * kLdsDigits + dk]),
+                                    (unsigned long long)dhi);
+            }
+          } else {
+            apply<G, true>(&cnt[s], &val[kVal ? s : 0], &dig[0], &flags[0], ivv[r], fvv[r]);
+          }
         } else {
           const int64_t g = global_slot(t, kk[r]);
           if (g >= 0) apply_global<G>(t, g, ivv[r], fvv[r]);
@@ -530,9 +562,9 @@ struct LdsTable {
       if constexpr (G == G_MAX_INT || G == G_MAX_F32) atomicMax(reinterpret_cast<long long*>(t.val + g), (long long)val[e]);
       if constexpr (kDig) {
         if (flags[e]) atomicOr(t.flags + g, flags[e]);
-        for (int d = 0; d < kDigits; ++d) {
-          const int64_t v = dig[e * kDigits + d];
-          if (v) atomicAdd(reinterpret_cast<unsigned long long*>(t.dig + g * kDigits + d), (unsigned long long)v);
+        for (int d = 0; d < kLdsDigits; ++d) {
+          const int64_t v = dig[e * kLdsDigits + d];
+          if (v) atomicAdd(reinterpret_cast<unsigned long long*>(t.dig + g * kDigits + d + 1), (unsigned long long)v);
         }
       }
     }

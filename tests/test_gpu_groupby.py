@@ -145,6 +145,25 @@ def test_groupby_float_sum_is_exact(agg):
     run_case(agg, keys, vals, "avg", max_groups=7, ctx="cancelling avg")
 
 
+def test_groupby_float_sum_full_exponent_range(agg):
+    """Float sums over every exponent, subnormals included: an LDS slot keeps
+    the middle digits only, and rows whose digits fall outside them (tiny and
+    huge magnitudes) take the global table; both halves must add up exactly,
+    on the direct and on the partitioned path."""
+    n = 300_007
+    r = np.random.default_rng(17)
+    e = r.integers(-149, 128, size=n)
+    m = 1.0 + r.random(n)
+    vals = (np.where(r.random(n) < 0.5, -1.0, 1.0) * np.ldexp(m, e)).astype(np.float32)
+    vals[~np.isfinite(vals)] = np.float32(3.0e38)
+    vals[::97] = np.float32(0.0)
+    assert (np.abs(vals[vals != 0]) < 2.0**-94).any() and (np.abs(vals) >= 2.0**98).any()
+    for card, mg in ((5, 5), (5, 100_000), (3000, 3000)):
+        keys = r.integers(0, card, size=n).astype(np.int32)
+        for op in ("sum", "avg"):
+            run_case(agg, keys, vals, op, max_groups=mg, ctx=f"exponent range card={card} plan={mg} {op}")
+
+
 def test_groupby_overflow_and_limits(agg):
     import torch
     keys = np.arange(1000, dtype=np.int64) * 7919
