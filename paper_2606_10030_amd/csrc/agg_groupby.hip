@@ -78,9 +78,9 @@ enum GOp { G_COUNT = 0, G_SUM_INT, G_MIN_INT, G_MAX_INT, G_SUM_F32, G_MIN_F32, G
 // LDS tables: one 1024-thread workgroup per CU with one table of up to
 // 148 KiB, on both paths: 8192 slots for 4-byte keys, 4096 for 8-byte keys
 // (twice that for COUNT, which keeps no value; 2048 for float sums, whose
-// slots carry 7 fixed-point digits).  Measured against three 256-thread workgroups per
-// CU with half the slots: fewer, larger tables hold 2x the groups at the same
-// load and fold faster.
+// slots carry 7 fixed-point digits).  Measured against three 256-thread
+// workgroups per CU with half the slots: fewer, larger tables hold 2x the
+// groups at the same load and fold faster.
 constexpr int kDirectThreads = 1024;
 constexpr int lds_slots_of(int g, int kd) {
   return g == G_SUM_F32 ? 2048 : (g == G_COUNT ? 2 : 1) * (kd == AGG_I32 ? 8192 : 4096);
@@ -521,7 +521,7 @@ struct LdsTable {
         if constexpr (kDig) in_lds = lds_digits_hold(fvv[r]);
         int s = -1;
         if (!in_lds) {
-          // digit 0 or 8: the global table below
+          // outside the LDS slot's digits: the global table below
         } else if (k == kMark) {
           s = L;
         } else {
@@ -864,9 +864,9 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   // quarter): the direct path up to half of its table, or in two passes over
   // the rows up to a whole table's worth, partitions sized for half of
   // theirs.  (Measured on 2^28 rows: two direct passes take 0.65x the
-  // partitioned path's time for int64 SUM, 0.86x for float sums, but 1.09x
-  // for COUNT, which moves the fewest bytes when partitioned; each pass costs
-  // about one direct run, so four would lose.)
+  // partitioned path's time for int64 SUM, about the same for float sums,
+  // but 1.09x for COUNT, which moves the fewest bytes when partitioned; each
+  // pass costs about one direct run, so four would lose.)
   int bits = 0, direct_sub_bits = 0;
   const int64_t half_table = lds_slots_of(g, key_dtype) / 2;
   if (max_groups > half_table && max_groups <= 2 * half_table && g != G_COUNT) {
