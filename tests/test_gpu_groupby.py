@@ -259,6 +259,36 @@ def test_groupby_result_independent_of_path(agg):
             assert got == first, f"{vdt} {op}: max_groups={mg} differs from max_groups=300"
 
 
+def test_groupby_plans_on_concurrent_streams(agg):
+    """Four plans (direct, two-pass, partitioned, sub-partition passes) run
+    at once on four streams, twice each, share no state: every result equals
+    the oracle's."""
+    import torch
+    n = 250_007
+    cases = []
+    for i, (card, mg, vdt, op) in enumerate(((100, 100, "i64", "sum"), (1500, 2000, "f32", "sum"),
+                                             (20_000, 20_000, "i32", "count"), (30_000, 6_000_000, "f32", "avg"))):
+        keys = make_keys(n, "i32", card, seed=60 + i)
+        vals = make_vals(n, vdt, seed=70 + i)
+        g = agg.GroupBy("i32", vdt, op, max_n=n, max_groups=mg)
+        out = torch.empty(mg * agg.GROUP_BYTES, dtype=torch.uint8, device="cuda")
+        ng = torch.zeros(1, dtype=torch.int64, device="cuda")
+        cases.append((g, torch.from_numpy(keys).to("cuda"), torch.from_numpy(vals).to("cuda"), out, ng,
+                      torch.cuda.Stream(), oracle.groupby(keys, vals, op), f"{vdt} {op} plan {mg}"))
+    torch.cuda.synchronize()
+    for _ in range(2):
+        for g, dk, dv, out, ng, st, _, _ in cases:
+            g.enqueue(dk, dv, out, ng, stream=st)
+    torch.cuda.synchronize()
+    for g, dk, dv, out, ng, st, want, ctx in cases:
+        k = int(ng.item())
+        raw = out[:k * agg.GROUP_BYTES].cpu().numpy().tobytes()
+        got = sorted(((x.key, x.i64, x.f64, x.count) for x in
+                      (agg.Group.from_buffer_copy(raw, i * agg.GROUP_BYTES) for i in range(k))), key=lambda t: t[0])
+        compare(got, want, ctx)
+        g.close()
+
+
 def test_groupby_multi_chunk_closed_form(agg):
     """More rows than one partitioning chunk (2^28), more groups than the
     direct path takes: per-key sums with closed forms."""
