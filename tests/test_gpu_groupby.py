@@ -289,6 +289,19 @@ def test_groupby_plans_on_concurrent_streams(agg):
         g.close()
 
 
+@pytest.mark.parametrize("kdt", ["i32", "i64"])
+def test_groupby_single_marker_key(agg, kdt):
+    """Every row has the key whose bit pattern marks an empty slot (INT32_MIN /
+    INT64_MIN): one group, through the direct path, the partitioned path (all
+    rows in one partition) and sub-partition passes."""
+    n = 200_003
+    keys = np.full(n, np.iinfo(NP[kdt]).min, dtype=NP[kdt])
+    for vdt, op in (("i64", "sum"), ("f32", "sum"), ("i32", "count")):
+        vals = make_vals(n, vdt, seed=81)
+        for mg in (1, 100_000, 6_000_000):
+            run_case(agg, keys, vals, op, max_groups=mg, ctx=f"marker key {kdt} {vdt} {op} plan {mg}")
+
+
 def test_groupby_multi_chunk_closed_form(agg):
     """More rows than one partitioning chunk (2^28), more groups than the
     direct path takes: per-key sums with closed forms."""
