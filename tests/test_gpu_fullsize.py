@@ -183,3 +183,61 @@ def test_groupby_full_size(agg, card):
         say(f"  {op}({vdt}): {len(got)} groups checked at {time.time() - t0:.1f}s")
     del keys_d
     free()
+
+
+def test_batch_full_size(agg):
+    """The benchmark's batch: 4096 columns, lengths log-uniform in [1e3, 1e7]
+    (4.48e9 items, 23.7 GB), dtype and function drawn as the benchmark draws
+    them, in the autotuned launch shape it times.  Every column's result equals
+    a single agg_run of that column bit for bit and passes the oracle check."""
+    import torch
+    from aggcheck import check, same_bits
+    t0 = time.time()
+    r = np.random.default_rng(12)
+    ncols = 4096
+    lens = np.floor(np.exp(r.uniform(np.log(1e3), np.log(1e7), ncols))).astype(np.int64)
+    dts = [["i32", "i64", "f32"][i] for i in r.integers(0, 3, ncols)]
+    ops = [["sum", "min", "max", "avg"][i] for i in r.integers(0, 4, ncols)]
+    host = [datagen.column(int(n), dt, "uniform", seed=1000 + i) for i, (dt, n) in enumerate(zip(dts, lens))]
+    dev = [torch.from_numpy(x).to("cuda") for x in host]
+    say(f"batch: {ncols} columns, {int(lens.sum())} items generated and copied in {time.time() - t0:.1f}s")
+    b = agg.Batch([agg.BatchColumn(d, op) for d, op in zip(dev, ops)])
+    b.autotune()
+    got = b.run()
+    say(f"batch: tuned {b.info()['tune']} at {time.time() - t0:.1f}s")
+    plans = {}
+    for i, (x, d, dt, op) in enumerate(zip(host, dev, dts, ops)):
+        if (dt, op) not in plans:
+            plans[(dt, op)] = agg.Plan(dt, op, max_n=int(lens.max()))
+        single = plans[(dt, op)].run(d)
+        assert same_bits(got[i], single), f"column {i} ({dt} {op} n={x.size}): batch != agg_run"
+        check(x, dt, op, "neumaier", got[i], ctx=f"batch column {i} ({dt} {op} n={x.size})")
+    for p in plans.values():
+        p.close()
+    b.close()
+    del dev
+    free()
+    say(f"batch: {ncols} columns checked in {time.time() - t0:.1f}s")
+
+
+def test_filter_full_size(agg):
+    """The benchmark's fused-filter cells on 2^30 items (SUM(x) WHERE y < 0 for
+    int32 x / float32 y, int64 x / int32 y, float32 x / int32 y, the uniform
+    columns the benchmark reads): each against the oracle on x[y < 0]."""
+    import torch
+    t0 = time.time()
+    cols = {dt: pinned_column(N, dt, "uniform", seed) for dt, seed in (("i32", 2), ("i64", 3), ("f32", 4))}
+    dev = {dt: h.to("cuda") for dt, h in cols.items()}
+    say(f"filter: columns generated and copied in {time.time() - t0:.1f}s")
+    for vdt, fdt in (("i32", "f32"), ("i64", "i32"), ("f32", "i32")):
+        filt = agg.make_filter(dev[fdt], None, 0, True, False)
+        plan = agg.Plan(vdt, "sum", max_n=N)
+        got = plan.run_filtered(dev[vdt], filt)
+        plan.close()
+        sel = cols[vdt].numpy()[cols[fdt].numpy() < 0]
+        assert got["count"] == sel.size, f"SUM({vdt}) WHERE {fdt} < 0: selected {got['count']} != {sel.size}"
+        check(sel, vdt, "sum", "neumaier", got, ctx=f"SUM({vdt}) WHERE {fdt} < 0")
+        del sel
+        say(f"  SUM({vdt}) WHERE {fdt} < 0 checked at {time.time() - t0:.1f}s")
+    del dev, cols
+    free()
