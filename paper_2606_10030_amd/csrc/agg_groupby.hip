@@ -72,6 +72,15 @@ constexpr int tile_rows() {
                : (KD == AGG_I32 ? 4 : 8) + (VD == AGG_I64 ? 8 : 4) == 12 ? 10240 : 8192;
 }
 constexpr int kBigTileBits = 7;  // key-only tiles grow from 128 partitions on
+// A staged row with a value is stored as one record, the key's 32-bit words
+// then the value's (8, 12 or 16 bytes, over the keys' and the values'
+// staging regions together), so a partition's run in a scatter tile is one
+// contiguous run instead of two.
+template <int KD, int VD>
+struct StagedRow {
+  static constexpr int KW = KD == AGG_I32 ? 1 : 2, VW = VD == AGG_I64 ? 2 : 1;
+  uint32_t w[KW + VW];
+};
 
 enum GOp { G_COUNT = 0, G_SUM_INT, G_MIN_INT, G_MAX_INT, G_SUM_F32, G_MIN_F32, G_MAX_F32 };
 
@@ -445,8 +454,18 @@ __global__ void __launch_bounds__(kTileThreads) gb_scatter_tiled_kernel(Args a) 
       else q = spart[j];
       const uint32_t pos = cur[q] + (uint32_t)j - toff[q];
       if ((int64_t)pos >= a.n) continue;  // cannot happen: counts match the histogram
-      static_cast<KT*>(a.pt.pk)[pos] = skey[j];
-      if constexpr (HASV) static_cast<VT*>(a.pt.pv)[pos] = sval[j];
+      if constexpr (HASV) {
+        using SR = StagedRow<KD, VD>;
+        SR row;
+        const uint64_t kb = (uint64_t)(int64_t)skey[j], vb = (uint64_t)sval[j];
+        row.w[0] = (uint32_t)kb;
+        if constexpr (SR::KW == 2) row.w[1] = (uint32_t)(kb >> 32);
+        row.w[SR::KW] = (uint32_t)vb;
+        if constexpr (SR::VW == 2) row.w[SR::KW + 1] = (uint32_t)(vb >> 32);
+        static_cast<SR*>(a.pt.pk)[pos] = row;
+      } else {
+        static_cast<KT*>(a.pt.pk)[pos] = skey[j];
+      }
     }
     __syncthreads();
     for (int e = tid; e < P; e += kTileThreads) {
@@ -491,7 +510,7 @@ struct LdsTable {
   // Rows first, first + step, ... below last whose key hash has the bits
   // (hash >> sub_shift) & sub_mask equal to sub; a row whose key finds no
   // slot within kLdsProbes goes to the global table.
-  template <int VD>
+  template <int VD, bool ROWS = false>  // ROWS: keys holds staged (key, value) records
   __device__ void fold_rows(const Table& t, const void* keys, const void* vals, int64_t first, int64_t last,
                             int64_t step, uint32_t sub_shift, uint32_t sub_mask, uint32_t sub) {
     constexpr int R = kAggRows;
@@ -503,12 +522,22 @@ struct LdsTable {
         // rows past the end re-load the last row (in bounds, never folded): no
         // branch around the loads, so all of them issue before the first wait
         const int64_t i = std::min<int64_t>(base + r * step, last - 1);
-        kk[r] = load_key<KD>(keys, i);
         ivv[r] = 0;
         fvv[r] = 0.0f;
-        if constexpr (G != G_COUNT) {
-          if constexpr (VD == AGG_F32) fvv[r] = static_cast<const float*>(vals)[i];
-          else ivv[r] = load_ival<VD>(vals, i);
+        if constexpr (ROWS && G != G_COUNT) {
+          using SR = StagedRow<KD, VD == AGG_I64 ? AGG_I64 : AGG_I32>;
+          const SR row = static_cast<const SR*>(keys)[i];
+          if constexpr (SR::KW == 2) kk[r] = (int64_t)(((uint64_t)row.w[1] << 32) | row.w[0]);
+          else kk[r] = (int64_t)(int32_t)row.w[0];
+          if constexpr (VD == AGG_F32) fvv[r] = __uint_as_float(row.w[SR::KW]);
+          else if constexpr (VD == AGG_I64) ivv[r] = (int64_t)(((uint64_t)row.w[SR::KW + 1] << 32) | row.w[SR::KW]);
+          else ivv[r] = (int64_t)(int32_t)row.w[SR::KW];
+        } else {
+          kk[r] = load_key<KD>(keys, i);
+          if constexpr (G != G_COUNT) {
+            if constexpr (VD == AGG_F32) fvv[r] = static_cast<const float*>(vals)[i];
+            else ivv[r] = load_ival<VD>(vals, i);
+          }
         }
       }
 #pragma unroll
@@ -633,8 +662,8 @@ __global__ void __launch_bounds__(kPartThreads) gb_aggregate_part_kernel(Args a)
     for (uint32_t sub = 0; sub <= sub_mask; ++sub) {
       tab.clear();
       __syncthreads();
-      tab.template fold_rows<VD>(a.t, a.pt.pk, a.pt.pv, r + threadIdx.x, seg_end, kPartThreads, sub_shift,
-                                     sub_mask, sub);
+      tab.template fold_rows<VD, true>(a.t, a.pt.pk, a.pt.pv, r + threadIdx.x, seg_end, kPartThreads, sub_shift,
+                                       sub_mask, sub);
       __syncthreads();
       tab.flush(a.t);
       __syncthreads();
@@ -919,7 +948,7 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   p->pt.tot = reinterpret_cast<uint32_t*>(take(b_tot));
   p->pt.start = reinterpret_cast<uint32_t*>(take(b_start));
   p->pt.pk = take(b_pk);
-  p->pt.pv = vw ? take(b_pv) : nullptr;
+  p->pt.pv = vw ? take(b_pv) : nullptr;  // right after pk: staged (key, value) records span both
   p->pt.bits = bits;
   p->pt.sub_bits = sub_bits;
   p->device = dev;
