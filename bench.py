@@ -46,10 +46,10 @@ def log(*a):
 def settle(torch):
     """Hand cached device memory back and wait before a section that copies
     from the host: for about a second after device memory is freed,
-    host-to-device copies run slower (most likely the driver clearing the freed
-    memory with the same copy engines; measured: the
-    64 MiB-chunk copy pipeline at 31 instead of 56 GB/s right after a 4 GiB
-    free, full speed 1 s later; zero-copy reads are unaffected)."""
+    host-to-device copies run slower (most likely the driver clearing the
+    freed memory with the same copy engines; measured: the 64 MiB-chunk copy
+    pipeline at 31 instead of 56 GB/s right after a 4 GiB free, full speed
+    1 s later; zero-copy reads are unaffected)."""
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     time.sleep(2.0)
