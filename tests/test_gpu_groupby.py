@@ -202,6 +202,17 @@ def test_groupby_errors(agg):
         g.run(k, k, n=200)                                                    # beyond max_n
     with pytest.raises(agg.AggError):
         g.run(np.zeros(10, np.int32).ctypes.data, k, n=10)                    # pageable host keys
+    raw = torch.zeros(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(agg.AggError):
+        g.run(raw.data_ptr() + 2, k, n=10)                                    # keys not 4-byte aligned
+    g64 = agg.GroupBy("i64", "i64", "sum", max_n=100, max_groups=10)
+    k64 = torch.zeros(100, dtype=torch.int64, device="cuda")
+    with pytest.raises(agg.AggError):
+        g64.run(k64, raw.data_ptr() + 4, n=10)                               # values not 8-byte aligned
+    got = g.run(k, k, n=100)                                                  # the plan still works
+    assert got == [(0, 0, 0.0, 100)]
+    g64.close()
+    g.close()
 
 
 def test_groupby_partitioned_with_few_actual_groups(agg):
