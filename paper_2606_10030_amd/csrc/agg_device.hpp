@@ -13,6 +13,7 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "agg.h"
 #include "agg_internal.hpp"
@@ -160,11 +161,30 @@ template <> struct Fold<K_SUM_F32_PLAIN> : FoldSumF32<false> {};
 template <> struct Fold<K_SUM_F32_F64C> : FoldSumF32<true> {};
 
 // Neumaier-compensated float32: (s, c) with s + c tracking the running sum.
+//
+// The correction c gathers the exact rounding errors of the s additions, but
+// c's own float32 additions round too; left alone, after m items those
+// roundings can reach about m^2 u^2 sum|x| (the quadratic term of the bound for
+// cascaded summation, Ogita, Rump and Oishi, SIAM J. Sci. Comput. 26(6),
+// 2005, Prop. 4.5).  So every kNeuRenormRounds rounds the pair is
+// renormalised by an exact two-sum, (s, c) <- (fl(s + c), error): the value
+// s + c is unchanged and |c| drops back to at most u |s|.  The correction then
+// only ever sums a few errors, and the rounding it adds is linear in m:
+// at most ceil(m / R) * R (R + 3) / 2 * u^2 * sum|x| for R rounds per block.
 struct NeuPair { float s, c; };
+constexpr int kNeuRenormRounds = 4;
 template <> struct Fold<K_SUM_F32_NEU> {
   static constexpr int W = 4, V = 4;
   using acc = NeuPair; using part = double;
   static __device__ acc identity() { return {0.0f, 0.0f}; }
+  // Knuth's two-sum: t = fl(a + b) and the exact error e = a + b - t, for
+  // operands of any magnitude (Knuth, TAOCP vol. 2, 4.2.2).  e is unique, so
+  // the pair does not depend on the operand order.
+  static __device__ __forceinline__ acc two_sum(float a, float b) {
+    const float t = a + b;
+    const float bb = t - a;
+    return {t, (a - (t - bb)) + (b - bb)};
+  }
   // Neumaier's update: the rounding error of s + x is recovered exactly by
   // subtracting in the order that puts the larger magnitude first.
   static __device__ __forceinline__ void add(acc& a, float x) {
@@ -175,20 +195,57 @@ template <> struct Fold<K_SUM_F32_NEU> {
     a.c += (big - t) + small;
     a.s = t;
   }
+  static __device__ __forceinline__ acc renorm(acc a) { return two_sum(a.s, a.c); }
   static __device__ void add_item(acc& a, const char* p) { add(a, load_item<float>(p)); }
   static __device__ void add_vec(acc* a, u32x4 x) { for (int k = 0; k < 4; ++k) add(a[k], as_f32(x[k])); }
-  // Two pairs: Knuth's two-sum gives the exact error e of s1 + s2 (unique,
-  // hence symmetric in the operands), which joins the corrections.
+  // Two renormalised pairs: the exact two-sum of the leading parts, its error
+  // joins the corrections, and the result is renormalised again.  Every step
+  // is symmetric in the operands, so merge(a, b) and merge(b, a) agree bit
+  // for bit.
   static __device__ acc merge(acc a, acc b) {
-    float t = a.s + b.s;
-    float bb = t - a.s;
-    float e = (a.s - (t - bb)) + (b.s - bb);
-    return {t, (a.c + b.c) + e};
+    const acc t = two_sum(a.s, b.s);
+    return two_sum(t.s, (a.c + b.c) + t.c);
   }
   static __device__ part to_part(acc a) { return (double)a.s + (double)a.c; }
   static __device__ part pidentity() { return 0.0; }
   static __device__ part pmerge(part a, part b) { return a + b; }
 };
+
+// Rounds a lane folds between two renormalisations of its accumulators
+// (0: the fold keeps no compensation to renormalise).
+template <int K>
+constexpr int renorm_rounds() { return K == K_SUM_F32_NEU ? kNeuRenormRounds : 0; }
+
+template <int K>
+__device__ __forceinline__ void renorm_all(typename Fold<K>::acc* a) {
+  if constexpr (K == K_SUM_F32_NEU) {
+#pragma unroll
+    for (int v = 0; v < Fold<K>::V; ++v) a[v] = Fold<K>::renorm(a[v]);
+  }
+}
+
+// After a lane has folded round r of its segment: renormalise when r closes a
+// block of renorm_rounds rounds.  The blocks are fixed by the round index, so
+// they fall at the same items whatever the number of loads in flight.
+template <int K>
+__device__ __forceinline__ void round_done(typename Fold<K>::acc* a, int64_t r) {
+  constexpr int R = renorm_rounds<K>();
+  if constexpr (R > 0) {
+    if ((r + 1) % R == 0) renorm_all<K>(a);
+  }
+}
+
+// The same inside an unrolled group of U rounds whose first round index is a
+// multiple of U (U a multiple of the block length): position u decides it at
+// compile time.
+template <int K, int U, int u>
+__device__ __forceinline__ void round_done_unrolled(typename Fold<K>::acc* a) {
+  constexpr int R = renorm_rounds<K>();
+  if constexpr (R > 0) {
+    static_assert(U % R == 0, "the unroll must hold whole renormalisation blocks");
+    if constexpr ((u + 1) % R == 0) renorm_all<K>(a);
+  }
+}
 
 template <bool IS_MIN> struct FoldMinMaxF32 {
   static constexpr int W = 4, V = 4;
@@ -278,6 +335,15 @@ __device__ __forceinline__ T wave_reduce(T x, M merge) {
 }
 
 // ------------------------------------------------------------ segment fold
+// Fold U loaded rounds in order (fold_round(u) folds round u of the group),
+// renormalising where a block closes.
+template <int K, int U, class FR, int... us>
+__device__ __forceinline__ void fold_unrolled(typename Fold<K>::acc* a, FR&& fold_round,
+                                              std::integer_sequence<int, us...>) {
+  ((fold_round(us), round_done_unrolled<K, U, us>(a)), ...);
+}
+
+
 // One wave folds one segment: lane l reads the 16-byte vectors at
 // seg + r * 1024 + 16 * l, r = 0, 1, ..., each component into its own
 // accumulator in order of r.  `valid` is the segment's byte count (a
@@ -306,10 +372,12 @@ __device__ __forceinline__ typename Fold<K>::acc fold_segment(const char* __rest
     u32x4 x[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) x[u] = load_vec<NT, AL, F::W>(p + (r + u) * kRoundBytes);
-#pragma unroll
-    for (int u = 0; u < U; ++u) F::add_vec(a, x[u]);
+    fold_unrolled<K, U>(a, [&](int u) { F::add_vec(a, x[u]); }, std::make_integer_sequence<int, U>());
   }
-  for (; r < full; ++r) F::add_vec(a, load_vec<NT, AL, F::W>(p + r * kRoundBytes));
+  for (; r < full; ++r) {
+    F::add_vec(a, load_vec<NT, AL, F::W>(p + r * kRoundBytes));
+    round_done<K>(a, r);
+  }
   const int rem = (int)(valid - full * kRoundBytes);
   if (rem > 0) {
     const int lo = lane * kVecBytes;
@@ -320,6 +388,7 @@ __device__ __forceinline__ typename Fold<K>::acc fold_segment(const char* __rest
       for (int k = 0; k * F::W < rem - lo; ++k) F::add_item(a[k], q + k * F::W);
     }
   }
+  renorm_all<K>(a);  // close the last block (the partial round joins it)
   if constexpr (F::V == 4) return F::merge(F::merge(a[0], a[1]), F::merge(a[2], a[3]));
   else return F::merge(a[0], a[1]);
 }

@@ -112,13 +112,15 @@ __device__ __forceinline__ typename Fold<K>::acc fold_segment_filtered(const cha
       if constexpr (!kCount) x[u] = load_vec<NT, AL, W>(p + (r + u) * kRoundBytes);
       load_filter<FB, FW, NT, AL>(f + (r + u) * RFB, fw[u]);
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) fold_round(kCount ? u32x4{0, 0, 0, 0} : x[u], fw[u]);
+    fold_unrolled<K, U>(
+        a, [&](int u) { fold_round(kCount ? u32x4{0, 0, 0, 0} : x[u], fw[u]); },
+        std::make_integer_sequence<int, U>());
   }
   for (; r < full; ++r) {
     uint32_t fw[FB / 4];
     load_filter<FB, FW, NT, AL>(f + r * RFB, fw);
     fold_round(kCount ? u32x4{0, 0, 0, 0} : load_vec<NT, AL, W>(p + r * kRoundBytes), fw);
+    round_done<K>(a, r);
   }
   const int rem = (int)(valid - full * kRoundBytes);
   if (rem > 0) {
@@ -142,6 +144,7 @@ __device__ __forceinline__ typename Fold<K>::acc fold_segment_filtered(const cha
     }
   }
   cnt = c;
+  renorm_all<K>(a);  // close the last block, as fold_segment does
   if constexpr (kCount) {
     return (typename F::acc)c;
   } else {

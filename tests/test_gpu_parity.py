@@ -191,3 +191,38 @@ def test_errors_on_device(agg):
     # the plan still works after rejected calls
     torch.cuda.synchronize()
     assert plan.run(x)["i64"] == 999 * 1000 // 2
+
+
+SHAPE_SIZES = [1, 5, 255, 256, 257, 1000, 1023, 1025, 4096 + 3, 65536 + 17, (1 << 20) + 7, (3 << 20) + 5,
+               10_000_019]
+
+
+@pytest.mark.parametrize("prec", ["neumaier", "f64_combine", "f32"])
+@pytest.mark.parametrize("dist", ["normal_outliers", "uniform"])
+def test_float_sum_follows_canonical_shape_bit_for_bit(agg, prec, dist):
+    """Float SUM bits equal the step-by-step numpy model of the documented
+    canonical shape (lane folds with renormalisation every 4 rounds, merge
+    trees, double combine), for aligned and unaligned addresses, in a batch
+    and through an always-true filter."""
+    import torch
+    import shape_model as sm
+    big = datagen.column(max(SHAPE_SIZES) + 1, "f32", dist, seed=41)
+    d = tdev(big)
+    plan = agg.Plan("f32", "sum", max_n=big.size, prec=prec)
+    ones = torch.ones(big.size, dtype=torch.int32, device="cuda")
+    always = agg.make_filter(ones, 1, 1, True, True)
+    say(f"shape {prec} {dist}")
+    for n in SHAPE_SIZES:
+        want = sm.model_sum(big[:n], prec)
+        got = plan.run(d[:n], n=n)["f64"]
+        assert got == want, f"{prec} {dist} n={n}: GPU {got!r} != model {want!r}"
+        got_u = plan.run(d[1:n + 1], n=n)["f64"]   # 4-byte aligned only: the item-wise path
+        assert got_u == sm.model_sum(big[1:n + 1], prec), f"{prec} {dist} n={n}: unaligned"
+        got_f = plan.run_filtered(d[:n], always, n=n)["f64"]
+        assert got_f == want, f"{prec} {dist} n={n}: filtered {got_f!r} != {want!r}"
+    cols = [agg.BatchColumn(d[:n], "sum", prec=prec) for n in SHAPE_SIZES[-4:]]
+    b = agg.Batch(cols)
+    for n, r in zip(SHAPE_SIZES[-4:], b.run()):
+        assert r["f64"] == sm.model_sum(big[:n], prec), f"batch {prec} n={n}"
+    b.close()
+    plan.close()
