@@ -59,8 +59,14 @@ enum { AGG_I32 = 0, AGG_I64 = 1, AGG_F32 = 2 };
 enum { AGG_SUM = 0, AGG_MIN = 1, AGG_MAX = 2, AGG_COUNT = 3, AGG_AVG = 4 };
 /* Float SUM / AVG precision modes (ignored for other dtype/op pairs):
  *   NEUMAIER     per-lane Neumaier-compensated float32 (sum, correction)
- *                pairs, combined across lanes by exact two-sum; each segment
- *                partial is sum + correction in double; double combine.
+ *                pairs, renormalised by an exact two-sum after every 4 rounds
+ *                of loads and after the last, combined across lanes by exact
+ *                two-sum (then renormalised); each segment partial is
+ *                sum + correction in double; double combine.  A-priori bound:
+ *                |error| <= 1.01 ((14 ceil(m/4) + 24) u^2 + (k + 8) v) sum|x|
+ *                with u = 2^-24, v = 2^-53, m = seg_bytes / 1024 items per
+ *                lane accumulator and k = ceil(nseg / 256); for 2^30 items
+ *                that is 6.5e-12 sum|x|.
  *   F32          plain float32 everywhere, including the final combine.
  *   F64_COMBINE  plain float32 lanes and wave reduction, segment partials
  *                widened to double, double combine. */
@@ -412,6 +418,29 @@ int agg_serve_simulate(const agg_serve_config* cfg, const agg_request* reqs, int
 /* ---- errors ---- */
 const char* agg_strerror(int32_t code);
 int32_t agg_last_hip_error(void);  /* hipError_t of the last AGG_E_HIP on this thread */
+
+/* ---- fault injection (tests of the error paths) ----
+ * Not part of the paper's method: it forces, from the host, failures the
+ * hardware rarely produces, so that tests can check that every call reports
+ * them with a status code and that plans, batches, group-by plans and
+ * servers stay usable afterwards.  A countdown per site: the countdown-th
+ * next event at the site fails (1 = the next one), 0 disarms it.
+ *   AGG_FAULT_ALLOC  a device or page-locked host allocation made by the
+ *                    library (agg_plan, agg_batch_plan, agg_groupby_plan,
+ *                    agg_serve_create, agg_autotune): the call returns
+ *                    AGG_E_NOMEM and allocates nothing.
+ *   AGG_FAULT_SHIP   the host-to-device copy of a chunk of a shipped serving
+ *                    request (agg_serve_run; in agg_serve_simulate, the
+ *                    simulated copy): that request ends with status AGG_E_HIP
+ *                    (agg_last_hip_error() = hipErrorUnknown), its arena
+ *                    region is freed and never cached, and later requests run
+ *                    normally.
+ * The failing runtime call is never issued, so nothing reaches the device.
+ * The environment variable AGG_FAULT_INJECT="alloc:n,ship:n" arms the
+ * countdowns at the library's first call; agg_fault_inject overrides it.
+ * Counters are process-wide; concurrent calls share them. */
+enum { AGG_FAULT_NONE = 0, AGG_FAULT_ALLOC = 1, AGG_FAULT_SHIP = 2, AGG_FAULT_SITES = 3 };
+int agg_fault_inject(int32_t site, int32_t countdown);
 
 #ifdef __cplusplus
 }

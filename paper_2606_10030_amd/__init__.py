@@ -186,6 +186,7 @@ def lib():
         "agg_pack_bound": ([i64, ctypes.POINTER(i64)], ctypes.c_int),
         "agg_pack_i32": ([vp, i64, vp, vp, i64, ctypes.POINTER(i64), i32], ctypes.c_int),
         "agg_run_packed": ([vp, ctypes.POINTER(Packed), vp, vp], ctypes.c_int),
+        "agg_fault_inject": ([i32, i32], ctypes.c_int),
         "agg_strerror": ([i32], ctypes.c_char_p),
         "agg_last_hip_error": ([], i32),
     }
@@ -201,6 +202,16 @@ def declared_symbols() -> list:
     """Every function declared in include/agg.h."""
     text = open(HEADER_PATH).read()
     return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(agg_\w+)\s*\(", text, re.M)))
+
+
+FAULT_SITES = {"alloc": 1, "ship": 2}
+
+
+def fault_inject(site, countdown: int) -> None:
+    """Make the countdown-th next event at `site` ("alloc": a library
+    allocation -> AGG_E_NOMEM; "ship": a shipped serving copy -> AGG_E_HIP for
+    that request) fail; 0 disarms it (agg_fault_inject)."""
+    _check(lib().agg_fault_inject(_code(site, FAULT_SITES, "fault site"), int(countdown)), "agg_fault_inject")
 
 
 def strerror(code: int) -> str:

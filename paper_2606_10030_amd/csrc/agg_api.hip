@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <limits>
 #include <cstdio>
@@ -14,6 +15,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "agg.h"
@@ -58,6 +60,72 @@ namespace agg {
 
 thread_local int32_t g_last_hip = 0;
 void record_hip_error(int32_t e) { g_last_hip = e; }
+
+// ------------------------------------------------------------ fault injection
+// Error paths that the hardware rarely takes are forced from the host: a
+// countdown per site makes the n-th next event there fail as the runtime
+// would report it (an allocation: out of memory; a shipped copy: a HIP
+// error).  Armed by agg_fault_inject or, at the first library call, by the
+// environment variable AGG_FAULT_INJECT="site:n[,site:n...]" (sites "alloc",
+// "ship").  Nothing reaches the device: the failing call is never issued.
+std::atomic<int32_t> g_fault[AGG_FAULT_SITES];
+std::once_flag g_fault_env_once;
+
+void fault_env() {
+  std::call_once(g_fault_env_once, [] {
+    const char* e = std::getenv("AGG_FAULT_INJECT");
+    if (!e) return;
+    const char* q = e;
+    while (*q) {
+      const char* colon = std::strchr(q, ':');
+      if (!colon) return;
+      const std::string site(q, (size_t)(colon - q));
+      const long n = std::strtol(colon + 1, nullptr, 10);
+      const int idx = site == "alloc" ? AGG_FAULT_ALLOC : site == "ship" ? AGG_FAULT_SHIP : -1;
+      if (idx > 0 && n > 0 && n < INT32_MAX) g_fault[idx].store((int32_t)n);
+      const char* comma = std::strchr(colon, ',');
+      if (!comma) return;
+      q = comma + 1;
+    }
+  });
+}
+
+bool fault_hit(int site) {
+  fault_env();
+  int32_t c = g_fault[site].load();
+  while (c > 0 && !g_fault[site].compare_exchange_weak(c, c - 1)) {
+  }
+  return c == 1;
+}
+
+int device_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (fault_hit(AGG_FAULT_ALLOC)) return AGG_E_NOMEM;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return AGG_E_NOMEM;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    g_last_hip = (int32_t)e;
+    return AGG_E_HIP;
+  }
+  return AGG_OK;
+}
+
+int pinned_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (fault_hit(AGG_FAULT_ALLOC)) return AGG_E_NOMEM;
+  if (hipHostMalloc(p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return AGG_E_NOMEM;
+  }
+  return AGG_OK;
+}
 
 #define HIPCHK(expr)                                  \
   do {                                                \
@@ -269,16 +337,7 @@ void batch_release(agg_batch_s* b) {
   delete b;
 }
 
-int alloc_device(void** p, size_t bytes) {
-  hipError_t e = hipMalloc(p, bytes);
-  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return AGG_E_NOMEM;
-  }
-  HIPCHK(e);
-  return AGG_OK;
-}
+int alloc_device(void** p, size_t bytes) { return device_alloc(p, bytes); }
 
 #define RET_IF(x)            \
   do {                       \
@@ -866,6 +925,13 @@ int agg_batch_autotune(agg_batch_t b, void* stream_v, agg_tune* best, double* be
   RET_IF(batch_capture(b, best_t));
   if (best) *best = best_t;
   if (best_ms_out) *best_ms_out = best_ms;
+  return AGG_OK;
+}
+
+int agg_fault_inject(int32_t site, int32_t countdown) {
+  if (site <= AGG_FAULT_NONE || site >= AGG_FAULT_SITES || countdown < 0) return AGG_E_INVALID;
+  fault_env();  // the environment is read first, so this call wins over it
+  g_fault[site].store(countdown);
   return AGG_OK;
 }
 

@@ -926,10 +926,10 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
                         b_pk + b_pv;
   agg_groupby_s* p = new (std::nothrow) agg_groupby_s();
   if (!p) return AGG_E_NOMEM;
-  if (hipMalloc(&p->ws, (size_t)total) != hipSuccess) {
-    (void)hipGetLastError();
+  const int arc = device_alloc(&p->ws, (size_t)total);
+  if (arc != AGG_OK) {
     delete p;
-    return AGG_E_NOMEM;
+    return arc;
   }
   char* c = static_cast<char*>(p->ws);
   auto take = [&c](int64_t bytes) {

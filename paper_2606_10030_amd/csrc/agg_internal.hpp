@@ -126,6 +126,9 @@ int unroll_index(int32_t unroll);                      // 0..3 for 4,8,16,32; -1
 
 // Host helpers shared by the runtime files.
 void record_hip_error(int32_t e);                 // remembered for agg_last_hip_error
+bool fault_hit(int site);                         // an injected failure is due at this site (agg_fault_inject)
+int device_alloc(void** p, size_t bytes);         // hipMalloc: AGG_OK / AGG_E_NOMEM (also when injected) / AGG_E_HIP
+int pinned_alloc(void** p, size_t bytes);         // hipHostMalloc: AGG_OK / AGG_E_NOMEM
 int current_device(int* dev);                     // current HIP device, checked to be gfx950
 int device_cu(int dev);                           // its compute-unit count
 void shape_of(int32_t dtype, int64_t n, agg_shape* s);

@@ -184,7 +184,7 @@ class Scheduler {
         }
         rs.done_s = ex_.now();
         last = std::max(last, rs.done_s);
-        release(j);
+        release(j, st > 0);
         busy[s] = false;
         --nbusy;
         nship -= j.ship ? 1 : 0;
@@ -245,7 +245,7 @@ class Scheduler {
         if (rc != AGG_OK) {
           rs.status = rc;
           rs.done_s = ex_.now();
-          release(j);
+          release(j, false);
           ++failed;
           ++finished;
         } else {
@@ -275,13 +275,16 @@ class Scheduler {
   }
 
  private:
-  void release(const Job& j) {
+  // The job's memory after it ended.  Only a shipped column whose request
+  // succeeded may enter the cache: after a failed copy (or a failed start)
+  // the region holds partial data, so it goes back to the arena.
+  void release(const Job& j, bool ok) {
     if (j.cached) {
       if (CacheEntry* c = cache_.lookup(reqs_id(j), j.bytes)) c->users--;
       return;
     }
     if (!j.ship) return;
-    if (cfg_.cache_shipped && cache_.insert(cur_ids_[j.req], j.off, j.bytes)) return;
+    if (ok && cfg_.cache_shipped && cache_.insert(cur_ids_[j.req], j.off, j.bytes)) return;
     arena_.release(j.off, j.bytes);
   }
   int64_t reqs_id(const Job& j) { return cur_ids_[j.req]; }
@@ -352,20 +355,28 @@ class HipExecutor : public Executor {
 class SimExecutor : public Executor {
  public:
   SimExecutor(int slots, double pcie_gbs, double hbm_gbs, double launch_s)
-      : done_at_(slots, -1.0), pcie_(pcie_gbs * 1e9), hbm_(hbm_gbs * 1e9), launch_(launch_s) {}
+      : done_at_(slots, -1.0), failing_(slots, false), pcie_(pcie_gbs * 1e9), hbm_(hbm_gbs * 1e9),
+        launch_(launch_s) {}
   int start(int slot, const agg_request& r, const Job& j) override {
     const double scan = (double)j.bytes / hbm_;
     double end = t_ + launch_ + scan;
+    failing_[slot] = false;
     if (j.ship) {  // one shared link; the scan of the last chunk follows the copy
       const double begin = std::max(t_, link_free_);
       link_free_ = begin + (double)j.bytes / pcie_;
       end = std::max(end, link_free_ + launch_);
+      failing_[slot] = fault_hit(AGG_FAULT_SHIP);  // the copy fails: the job ends with an error
     }
     done_at_[slot] = end;
     n_[slot] = r.n;
     return AGG_OK;
   }
-  int poll(int slot) override { return done_at_[slot] >= 0 && t_ >= done_at_[slot] ? 1 : 0; }
+  int poll(int slot) override {
+    if (done_at_[slot] < 0 || t_ < done_at_[slot]) return 0;
+    if (!failing_[slot]) return 1;
+    done_at_[slot] = -1.0;
+    return AGG_E_HIP;
+  }
   void finish(int slot, agg_result* out) override {
     std::memset(out, 0, sizeof *out);
     out->count = n_[slot];
@@ -383,6 +394,7 @@ class SimExecutor : public Executor {
 
  private:
   std::vector<double> done_at_;
+  std::vector<bool> failing_;
   std::map<int, int64_t> n_;
   double pcie_, hbm_, launch_;
   double t_ = 0.0, link_free_ = 0.0;
@@ -460,6 +472,10 @@ int agg::serve::HipExecutor::copy_chunk(int slot, int64_t k) {
   const int64_t lo = k * r.cs, hi = std::min(r.nseg, lo + r.cs);
   const int64_t b0 = lo * r.seg_bytes;
   const int64_t nb = std::min(r.bytes, hi * r.seg_bytes) - b0;
+  if (fault_hit(AGG_FAULT_SHIP)) {  // an injected copy failure: the copy is never issued
+    record_hip_error((int32_t)hipErrorUnknown);
+    return AGG_E_HIP;
+  }
   // chunk k + kPipe is issued on this stream only after chunk k was seen complete
   const hipError_t e =
       hipMemcpyAsync(r.dst + b0, r.host + b0, (size_t)nb, hipMemcpyHostToDevice, s_->copy[slot][k % kPipe]);
@@ -582,25 +598,11 @@ int agg_serve_create(agg_server_t* out, const agg_serve_config* cfg) {
     return rc;
   };
   hipError_t e;
-  if (cfg->hbm_budget_bytes > 0) {
-    e = hipMalloc(reinterpret_cast<void**>(&s->arena), (size_t)cfg->hbm_budget_bytes);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      s->arena = nullptr;
-      return fail(AGG_E_NOMEM);
-    }
-  }
-  if ((e = hipMalloc(reinterpret_cast<void**>(&s->part), (size_t)cfg->max_slots * kSegTarget * 8)) != hipSuccess) {
-    (void)hipGetLastError();
-    s->part = nullptr;
-    return fail(AGG_E_NOMEM);
-  }
-  if ((e = hipHostMalloc(reinterpret_cast<void**>(&s->res_host), sizeof(agg_result) * cfg->max_slots,
-                         hipHostMallocDefault)) != hipSuccess) {
-    (void)hipGetLastError();
-    s->res_host = nullptr;
-    return fail(AGG_E_NOMEM);
-  }
+  int arc = AGG_OK;
+  if (cfg->hbm_budget_bytes > 0) arc = device_alloc(reinterpret_cast<void**>(&s->arena), (size_t)cfg->hbm_budget_bytes);
+  if (arc == AGG_OK) arc = device_alloc(reinterpret_cast<void**>(&s->part), (size_t)cfg->max_slots * kSegTarget * 8);
+  if (arc == AGG_OK) arc = pinned_alloc(reinterpret_cast<void**>(&s->res_host), sizeof(agg_result) * cfg->max_slots);
+  if (arc != AGG_OK) return fail(arc);
   for (int i = 0; i < cfg->max_slots; ++i) {
     s->slots = i + 1;
     e = hipStreamCreateWithFlags(&s->comp[i], hipStreamNonBlocking);

@@ -173,10 +173,8 @@ int agg_autotune(int32_t dtype, int32_t op, int32_t prec, const void* col, int64
     cands = kernel_candidates(kind);
   }
   void* out = nullptr;
-  if (hipMalloc(&out, sizeof(agg_result)) != hipSuccess) {
-    (void)hipGetLastError();
-    return AGG_E_NOMEM;
-  }
+  const int arc = device_alloc(&out, sizeof(agg_result));
+  if (arc != AGG_OK) return arc;
   const int64_t bytes = n * width_of(dtype);
   double best_ms = -1.0;
   agg_tune best_t{};

@@ -126,3 +126,65 @@ def test_shipping_cap_keeps_resident_latency_low():
             peak = max(peak, live)
         assert peak <= cap
     assert out[2] < out[8]
+
+
+def test_failed_shipped_request_is_not_cached():
+    """A shipped request whose copy fails ends with AGG_E_HIP and leaves no
+    cache entry: the next request for the same column ships it again (and
+    that one, having succeeded, is then cached)."""
+    n = 1 << 24
+    reqs = reqs_of([dict(n=n, arrival_s=0.0, column_id=7), dict(n=n, arrival_s=1.0, column_id=7),
+                    dict(n=n, arrival_s=2.0, column_id=7)])
+    agg.fault_inject("ship", 1)
+    try:
+        st, sm = agg.serve_simulate(reqs, hbm_budget_bytes=1 << 30, max_slots=2, cache_shipped=True)
+    finally:
+        agg.fault_inject("ship", 0)
+    assert [s["status"] for s in st] == [agg.E_HIP, 0, 0]
+    assert [s["cache_hit"] for s in st] == [0, 0, 1]
+    assert [s["bytes_shipped"] for s in st] == [4 * n, 4 * n, 0]
+    assert sm["failed"] == 1 and sm["completed"] == 2 and sm["cache_hits"] == 1
+    # the failed request's region went back to the arena: a budget of one
+    # column still serves the rest
+    agg.fault_inject("ship", 1)
+    try:
+        st, sm = agg.serve_simulate(reqs, hbm_budget_bytes=4 * n, max_slots=2, cache_shipped=True)
+    finally:
+        agg.fault_inject("ship", 0)
+    assert [s["status"] for s in st] == [agg.E_HIP, 0, 0] and sm["peak_reserved_bytes"] <= 4 * n
+
+
+def test_fault_countdown_and_disarm():
+    reqs = reqs_of([dict(n=1 << 20, arrival_s=0.1 * i, column_id=i) for i in range(5)])
+    agg.fault_inject("ship", 3)           # the third shipped copy fails
+    try:
+        st, _ = agg.serve_simulate(reqs, hbm_budget_bytes=1 << 30, max_slots=1, cache_shipped=False)
+    finally:
+        agg.fault_inject("ship", 0)
+    assert [s["status"] for s in st] == [0, 0, agg.E_HIP, 0, 0]
+    st, _ = agg.serve_simulate(reqs, hbm_budget_bytes=1 << 30, max_slots=1, cache_shipped=False)
+    assert all(s["status"] == 0 for s in st)
+    with pytest.raises(agg.AggError):
+        agg.fault_inject(9, 1)
+    with pytest.raises(agg.AggError):
+        agg.fault_inject("ship", -1)
+
+
+def test_fault_injection_from_the_environment():
+    """AGG_FAULT_INJECT arms the countdowns at the library's first call (a
+    fresh process, so the variable is read)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_2606_10030_amd as agg\n"
+        "reqs = [dict(ptr=1 << 20, n=1 << 20, arrival_s=0.1 * i, dtype='i32', op='sum', resident=False,"
+        " column_id=i) for i in range(4)]\n"
+        "st, sm = agg.serve_simulate(reqs, hbm_budget_bytes=1 << 30, max_slots=1, cache_shipped=False)\n"
+        "print([s['status'] for s in st])\n" % root)
+    env = dict(os.environ, AGG_FAULT_INJECT="alloc:5,ship:2")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == f"[0, {agg.E_HIP}, 0, 0]"
