@@ -137,6 +137,43 @@ def groupby_profile_mode(cards):
     log("group-by profile mode done")
 
 
+POWER_MAX_W = 2800.0    # twice the MI355X board power: anything above is a misread
+ENERGY_MIN_SPAN_S = 2.0  # the counter advances about once a second
+
+
+def energy_power(edges, t_lo, t_hi, res_uj, max_w=POWER_MAX_W, min_span_s=ENERGY_MIN_SPAN_S):
+    """Average power (W) from the GPU's cumulative energy counter.
+
+    edges: [(time_s, counter)] at each observed change of the counter (one
+    count = res_uj microjoules).  Only updates inside [t_lo, t_hi] count.
+    Power comes from the intervals between consecutive updates: an interval
+    whose counter goes backwards or implies more than max_w (a misread value,
+    or a wrap) is dropped with its time, and the rest must span at least
+    min_span_s seconds.  Returns (watts, info) or (None, info) with a reason."""
+    inside = sorted((t, v) for t, v in edges if t_lo <= t <= t_hi)
+    used_dt = used_j = 0.0
+    used = rejected = 0
+    for (ta, va), (tb, vb) in zip(inside, inside[1:]):
+        dt = tb - ta
+        dj = (vb - va) * res_uj * 1e-6
+        if dt <= 0 or dj < 0 or dj > max_w * dt:
+            rejected += 1
+            continue
+        used += 1
+        used_dt += dt
+        used_j += dj
+    info = {"updates": len(inside), "intervals_used": used, "intervals_rejected": rejected,
+            "span_s": round(used_dt, 3)}
+    if len(inside) < 2:
+        return None, {**info, "reason": "fewer than 2 counter updates inside the window"}
+    if used_dt < min_span_s:
+        return None, {**info, "reason": f"usable counter intervals span {used_dt:.3f} s < {min_span_s} s"}
+    w = used_j / used_dt
+    if not (0.0 < w <= max_w):
+        return None, {**info, "reason": f"implausible average power {w:.4g} W"}
+    return w, info
+
+
 def bench_energy(agg, torch, dev_i32, host_i32, stream):
     """Joules per aggregation from the GPU's energy accumulator (amdsmi), for
     the on-device SUM of a 2^30-item int32 column and the same SUM end to end
@@ -144,10 +181,11 @@ def bench_energy(agg, torch, dev_i32, host_i32, stream):
 
     The accumulator advances about once a second, so each figure comes from a
     window of several seconds: the host keeps the GPU busy with scans issued
-    in batches and notes the time of every counter update; average power is
-    taken between the first and the last update that both fall inside the
-    busy window (never across its edges), and energy per scan = that power x
-    the measured time per scan."""
+    in batches and notes the time of every counter update; energy_power turns
+    the updates inside the window into an average power (or None with the
+    reason), and energy per scan = that power x the measured time per scan.
+    The socket power reading, sampled through the same windows, is reported
+    beside it as a cross-check."""
     try:
         import amdsmi
         amdsmi.amdsmi_init()
@@ -159,36 +197,56 @@ def bench_energy(agg, torch, dev_i32, host_i32, stream):
     def counter():
         return amdsmi.amdsmi_get_energy_count(h)["energy_accumulator"]
 
-    def power(edges, t_lo, t_hi):
-        inside = [(t, v) for t, v in edges if t_lo < t < t_hi]
-        if len(inside) < 2:
+    def socket_w():
+        try:
+            pi = amdsmi.amdsmi_get_power_info(h)
+        except Exception:
             return None
-        (ta, va), (tb, vb) = inside[0], inside[-1]
-        return (vb - va) * res * 1e-6 / (tb - ta)
+        for key in ("average_socket_power", "current_socket_power", "socket_power"):
+            v = pi.get(key) if isinstance(pi, dict) else None
+            if isinstance(v, (int, float)) and 0 < v <= POWER_MAX_W:
+                return float(v)
+        return None
 
-    def watch(edges, last):
-        v = counter()
-        if v != last[0]:
-            edges.append((time.perf_counter(), v))
-            last[0] = v
+    class Watch:
+        def __init__(self):
+            self.edges, self.last, self.sock, self.next_sock = [], counter(), [], 0.0
+
+        def poll(self):
+            now = time.perf_counter()
+            v = counter()
+            if v != self.last:
+                self.edges.append((now, v))
+                self.last = v
+            if now >= self.next_sock:
+                w = socket_w()
+                if w is not None:
+                    self.sock.append(w)
+                self.next_sock = now + 0.02
+
+        def socket_mean(self):
+            return round(statistics.mean(self.sock), 1) if self.sock else None
 
     out = {"available": True, "source": "amdsmi energy accumulator (whole GPU), updates about once a second",
-           "method": "power between counter updates inside a 3.5-5 s window, x time per scan"}
+           "method": "energy_power: counter intervals inside a 6 s idle / 5 s busy window (misreads dropped, "
+                     ">= 2 s of intervals, power in (0, 2800] W) x time per scan; socket power sampled "
+                     "every 20 ms as a cross-check"}
     torch.cuda.synchronize()
-    edges, last = [], [counter()]
+    w = Watch()
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < 3.5:
-        watch(edges, last)
+    while time.perf_counter() - t0 < 6.0:
+        w.poll()
         time.sleep(0.001)
-    idle_w = power(edges, t0, time.perf_counter())
+    idle_w, idle_info = energy_power(w.edges, t0, time.perf_counter(), res)
     out["idle_W"] = None if idle_w is None else round(idle_w, 1)
+    out["idle"] = {**idle_info, "socket_power_W_mean": w.socket_mean()}
     n = dev_i32.numel()
     o = torch.zeros(32, dtype=torch.uint8, device="cuda")
     for label, src, col, batch in (("on_device", "device", dev_i32, 200), ("end_to_end_zerocopy", "zerocopy", host_i32, 2)):
         p = agg.Plan("i32", "sum", max_n=n, src=src)
         p.enqueue(col, o, stream=stream)
         torch.cuda.synchronize()
-        edges, last, pending, scans = [], [counter()], [], 0
+        w, pending, scans = Watch(), [], 0
         t0 = time.perf_counter()
         while time.perf_counter() - t0 < 5.0 or pending:
             if time.perf_counter() - t0 < 5.0 and len(pending) < 3:
@@ -199,7 +257,7 @@ def bench_energy(agg, torch, dev_i32, host_i32, stream):
                 pending.append(ev)
                 scans += batch
             else:
-                watch(edges, last)
+                w.poll()
                 if pending and pending[0].query():
                     pending.pop(0)
                 else:
@@ -207,16 +265,17 @@ def bench_energy(agg, torch, dev_i32, host_i32, stream):
         t1 = time.perf_counter()
         p.close()
         per_scan_s = (t1 - t0) / scans
-        busy_w = power(edges, t0, t1)
+        busy_w, busy_info = energy_power(w.edges, t0, t1, res)
         gb = n * 4 / 1e9
+        rec = {"scans": scans, "seconds": round(t1 - t0, 2), "ms_per_scan": round(per_scan_s * 1e3, 3),
+               "counter": busy_info, "socket_power_W_mean": w.socket_mean()}
         if busy_w is None:
-            out[label] = {"scans": scans, "seconds": round(t1 - t0, 2), "J_per_scan": None}
+            out[label] = {**rec, "J_per_scan": None}
             continue
         per = busy_w * per_scan_s
-        out[label] = {"J_per_scan": round(per, 4),
+        out[label] = {**rec, "J_per_scan": round(per, 4),
                       "J_per_scan_above_idle": None if idle_w is None else round((busy_w - idle_w) * per_scan_s, 4),
-                      "J_per_GB": round(per / gb, 4), "avg_W": round(busy_w, 1), "scans": scans,
-                      "seconds": round(t1 - t0, 2), "ms_per_scan": round(per_scan_s * 1e3, 3),
+                      "J_per_GB": round(per / gb, 4), "avg_W": round(busy_w, 1),
                       "J_for_1.2e9_items": round(per * 1.2e9 / n, 4)}
     try:
         amdsmi.amdsmi_shut_down()

@@ -64,3 +64,41 @@ def test_bench_prints_one_contract_line():
     assert rf["traffic"] is None or rf["traffic"] >= rf["algorithmic_bytes_per_launch"]
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1 and cb["unit"] == "GB/s"
+
+
+def test_energy_power_from_counter_updates():
+    bench = load_bench()
+    res = 15.3                     # microjoules per count
+    per_s = 500.0 / (res * 1e-6)   # counts per second at 500 W
+    # updates once a second for 5 s
+    edges = [(10.0 + i, 1_000_000 + int(i * per_s)) for i in range(6)]
+    w, info = bench.energy_power(edges, 9.5, 16.0, res)
+    assert abs(w - 500.0) < 0.01 and info["intervals_used"] == 5 and info["intervals_rejected"] == 0
+    # updates outside the window do not count
+    w2, _ = bench.energy_power(edges + [(30.0, 10 ** 12)], 9.5, 16.0, res)
+    assert w2 == w
+
+
+def test_energy_power_rejects_close_updates_and_misreads():
+    bench = load_bench()
+    res = 15.3
+    # two updates milliseconds apart: too short a span, no value
+    w, info = bench.energy_power([(1.0, 100), (1.002, 100 + 65_000)], 0.0, 5.0, res)
+    assert w is None and "span" in info["reason"]
+    # a single update: no interval at all
+    w, info = bench.energy_power([(1.0, 100)], 0.0, 5.0, res)
+    assert w is None and "fewer than 2" in info["reason"]
+    # a misread (the counter jumps to a huge value, then back, then on): the
+    # two bad intervals are dropped with their time, the rest gives 300 W
+    per_s = 300.0 / (res * 1e-6)
+    good = [(float(i), int(i * per_s)) for i in range(8)]
+    bad = good[:3] + [(2.5, 2 ** 50)] + good[3:]
+    w, info = bench.energy_power(bad, -1.0, 10.0, res)
+    assert abs(w - 300.0) < 0.01 and info["intervals_rejected"] == 2
+    # a counter that goes backwards (wrap or reset) and then continues
+    wrap = good[:4] + [(4.0, 5)] + [(5.0 + i, 5 + int((i + 1) * per_s)) for i in range(3)]
+    w, info = bench.energy_power(wrap, -1.0, 10.0, res)
+    assert abs(w - 300.0) < 0.01 and info["intervals_rejected"] == 1
+    # an implausible average (every interval a jump) gives no value
+    w, info = bench.energy_power([(float(i), i * 10 ** 12) for i in range(5)], -1.0, 10.0, res)
+    assert w is None
