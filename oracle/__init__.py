@@ -80,6 +80,12 @@ def _load():
         lib.oracle_groupby.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                        ctypes.c_int64, ctypes.c_int, ctypes.POINTER(_Group), ctypes.c_int64]
         lib.oracle_groupby.restype = ctypes.c_int64
+        lib.oracle_block_aggregate.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int64, ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_block_aggregate.restype = ctypes.c_int
+        lib.oracle_read_ceiling.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_uint64)]
+        lib.oracle_read_ceiling.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -148,3 +154,75 @@ def groupby(keys: np.ndarray, vals: np.ndarray, op) -> list:
     ng2 = lib.oracle_groupby(keys.ctypes.data if n else None, kd, vals.ctypes.data if n else None, vd, n, o, out, ng)
     assert ng2 == ng
     return [(out[i].key, out[i].i64, out[i].f64, out[i].count) for i in range(ng)]
+
+
+def block_table_ptr(ptr: int, n: int, dtype: int, op, block: int, threads: int | None = None) -> np.ndarray:
+    """Per-block SUM (mod 2^64) / MIN / MAX of the integer items at host address
+    ``ptr``: entry j covers items [j*block, min((j+1)*block, n))."""
+    o = OPS[op] if isinstance(op, str) else int(op)
+    out = np.empty(max(1, -(-n // block)), dtype=np.int64)
+    rc = _load().oracle_block_aggregate(ctypes.c_void_p(ptr), n, int(dtype), o, block, out.ctypes.data,
+                                        threads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle_block_aggregate rc={rc}")
+    return out[: -(-n // block)]
+
+
+def block_table(col: np.ndarray, op, block: int, threads: int | None = None) -> np.ndarray:
+    col = np.ascontiguousarray(col)
+    return block_table_ptr(col.ctypes.data if col.size else 0, col.size, _NP[col.dtype], op, block, threads)
+
+
+class RangeOracle:
+    """Exact SUM / MIN / MAX / COUNT / AVG of sub-ranges [off, off + n) of one
+    large integer column: whole blocks from the oracle's block tables, the
+    partial end blocks from oracle_aggregate on those items.  Results as
+    ``aggregate`` returns them."""
+
+    def __init__(self, ptr: int, n: int, dtype: int, block: int = 1 << 16, threads: int | None = None):
+        self.ptr, self.n, self.dtype, self.block = ptr, n, int(dtype), block
+        self.width = 4 if self.dtype == I32 else 8
+        s = block_table_ptr(ptr, n, dtype, SUM, block, threads)
+        self.prefix = np.concatenate([np.zeros(1, np.uint64), np.cumsum(s.astype(np.uint64), dtype=np.uint64)])
+        self.bmin = block_table_ptr(ptr, n, dtype, MIN, block, threads)
+        self.bmax = block_table_ptr(ptr, n, dtype, MAX, block, threads)
+
+    def _part(self, lo: int, hi: int, op: int) -> OracleResult:
+        return aggregate_ptr(self.ptr + self.width * lo, hi - lo, self.dtype, op, 1)
+
+    def aggregate(self, off: int, n: int, op) -> OracleResult:
+        o = OPS[op] if isinstance(op, str) else int(op)
+        if not (0 <= off and off + n <= self.n and n >= 0):
+            raise ValueError("range outside the column")
+        if o == COUNT or n == 0:
+            return aggregate_ptr(self.ptr + self.width * off, n, self.dtype, o, 1)
+        lo, hi = off, off + n
+        b0, b1 = -(-lo // self.block), hi // self.block      # whole blocks [b0, b1)
+        if b0 >= b1:
+            return self._part(lo, hi, o)
+        parts = [self._part(lo, b0 * self.block, SUM if o == AVG else o) if lo < b0 * self.block else None,
+                 self._part(b1 * self.block, hi, SUM if o == AVG else o) if b1 * self.block < hi else None]
+        parts = [p for p in parts if p is not None]
+        if o in (SUM, AVG):
+            s = (int(self.prefix[b1]) - int(self.prefix[b0])) % (1 << 64)
+            for p in parts:
+                s += p.i64
+            s = (s + (1 << 63)) % (1 << 64) - (1 << 63)
+            if o == SUM:
+                return OracleResult(s, float(s), n, False)
+            return OracleResult(0, float(s) / float(n), n, False)
+        ext = (min if o == MIN else max)
+        v = int(self.bmin[b0:b1].min()) if o == MIN else int(self.bmax[b0:b1].max())
+        for p in parts:
+            v = ext(v, p.i64)
+        return OracleResult(v, float(v), n, False)
+
+
+def read_ceiling(buf_ptr: int, nbytes: int, threads: int) -> int:
+    """Read nbytes of host memory with `threads` threads (the host memory read
+    ceiling of the CPU baseline); returns the xor of the words read."""
+    x = ctypes.c_uint64()
+    rc = _load().oracle_read_ceiling(ctypes.c_void_p(buf_ptr), nbytes, threads, ctypes.byref(x))
+    if rc != 0:
+        raise ValueError(f"oracle_read_ceiling rc={rc}")
+    return int(x.value)

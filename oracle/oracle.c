@@ -350,3 +350,110 @@ int64_t oracle_groupby(const void* keys, int key_dtype, const void* vals, int va
     free(idx);
     return ngroups;
 }
+
+/* ------------------------------------------------------------------ */
+/* Block tables: out[j] = SUM (mod 2^64), MIN or MAX of the integer items
+ * col[j*block, min((j+1)*block, n)), for j = 0 .. ceil(n/block) - 1 -- the
+ * same definitions as oracle_aggregate, applied to each block.  They let a
+ * test check many aggregations of sub-ranges of one large column: a range is
+ * its partial end blocks (aggregated directly) plus whole blocks (combined
+ * from the table; exact, since sum mod 2^64, min and max are associative). */
+
+typedef struct {
+    const void* col;
+    int64_t n, block, jlo, jhi;
+    int dtype, op;
+    int64_t* out;
+} block_job;
+
+static void* block_worker(void* arg) {
+    block_job* b = (block_job*)arg;
+    for (int64_t j = b->jlo; j < b->jhi; ++j) {
+        const int64_t lo = j * b->block;
+        const int64_t hi = lo + b->block < b->n ? lo + b->block : b->n;
+        uint64_t wrap = 0;
+        int64_t mn = INT64_MAX, mx = INT64_MIN;
+        for (int64_t i = lo; i < hi; ++i) {
+            const int64_t x = item_i64(b->col, b->dtype, i);
+            wrap += (uint64_t)x;
+            if (x < mn) mn = x;
+            if (x > mx) mx = x;
+        }
+        b->out[j] = b->op == O_SUM ? (int64_t)wrap : (b->op == O_MIN ? mn : mx);
+    }
+    return NULL;
+}
+
+int oracle_block_aggregate(const void* col, int64_t n, int dtype, int op, int64_t block, int64_t* out,
+                           int nthreads) {
+    if (n < 0 || (n > 0 && (!col || !out)) || block < 1) return O_EINVAL;
+    if ((dtype != O_I32 && dtype != O_I64) || (op != O_SUM && op != O_MIN && op != O_MAX)) return O_EINVAL;
+    const int64_t nb = (n + block - 1) / block;
+    int nt = nthreads < 1 ? 1 : (nthreads > 256 ? 256 : nthreads);
+    if (nb < nt) nt = nb > 0 ? (int)nb : 1;
+    block_job* jobs = (block_job*)calloc((size_t)nt, sizeof(block_job));
+    pthread_t* th = (pthread_t*)calloc((size_t)nt, sizeof(pthread_t));
+    if (!jobs || !th) { free(jobs); free(th); return O_ENOMEM; }
+    for (int t = 0; t < nt; ++t) {
+        jobs[t] = (block_job){col, n, block, nb * t / nt, nb * (t + 1) / nt, dtype, op, out};
+    }
+    int started = 0;
+    for (int t = 1; t < nt; ++t) {
+        if (pthread_create(&th[t], NULL, block_worker, &jobs[t])) break;
+        started = t;
+    }
+    for (int t = started + 1; t < nt; ++t) block_worker(&jobs[t]);
+    block_worker(&jobs[0]);
+    for (int t = 1; t <= started; ++t) pthread_join(th[t], NULL);
+    free(jobs);
+    free(th);
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Host memory read ceiling for the CPU baseline: `nthreads` threads read
+ * contiguous ranges of the buffer 64 bits at a time (8 independent xor
+ * chains each, so the loop is bound by memory, not by a dependency); the xor
+ * of everything is returned so the reads cannot be dropped.  Not part of any
+ * aggregation result. */
+
+typedef struct {
+    const uint64_t* p;
+    int64_t lo, hi;
+    uint64_t acc;
+} read_job;
+
+static void* read_worker(void* arg) {
+    read_job* r = (read_job*)arg;
+    uint64_t a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t i = r->lo;
+    for (; i + 8 <= r->hi; i += 8)
+        for (int k = 0; k < 8; ++k) a[k] ^= r->p[i + k];
+    for (; i < r->hi; ++i) a[0] ^= r->p[i];
+    r->acc = a[0] ^ a[1] ^ a[2] ^ a[3] ^ a[4] ^ a[5] ^ a[6] ^ a[7];
+    return NULL;
+}
+
+int oracle_read_ceiling(const void* buf, int64_t bytes, int nthreads, uint64_t* xor_out) {
+    if (bytes < 0 || (bytes > 0 && !buf) || !xor_out) return O_EINVAL;
+    const int64_t words = bytes / 8;
+    int nt = nthreads < 1 ? 1 : (nthreads > 256 ? 256 : nthreads);
+    read_job* jobs = (read_job*)calloc((size_t)nt, sizeof(read_job));
+    pthread_t* th = (pthread_t*)calloc((size_t)nt, sizeof(pthread_t));
+    if (!jobs || !th) { free(jobs); free(th); return O_ENOMEM; }
+    for (int t = 0; t < nt; ++t) jobs[t] = (read_job){(const uint64_t*)buf, words * t / nt, words * (t + 1) / nt, 0};
+    int started = 0;
+    for (int t = 1; t < nt; ++t) {
+        if (pthread_create(&th[t], NULL, read_worker, &jobs[t])) break;
+        started = t;
+    }
+    for (int t = started + 1; t < nt; ++t) read_worker(&jobs[t]);
+    read_worker(&jobs[0]);
+    for (int t = 1; t <= started; ++t) pthread_join(th[t], NULL);
+    uint64_t x = 0;
+    for (int t = 0; t < nt; ++t) x ^= jobs[t].acc;
+    *xor_out = x;
+    free(jobs);
+    free(th);
+    return O_OK;
+}

@@ -16,6 +16,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
+import datagen
 import oracle
 from oracle import AVG, COUNT, F32, I32, I64, MAX, MIN, SUM
 
@@ -210,3 +211,48 @@ def test_superaccumulator_digit_headroom():
     exp = correctly_rounded(Fraction(float(fmax)) + 1)
     assert oracle.value(x, "sum") == exp
     assert oracle.value(x[:-1], "sum") == float(fmax)
+
+
+# ---- block tables and sub-range aggregation (for checking many ranges of one large column)
+@pytest.mark.parametrize("dtype", ["i32", "i64"])
+def test_block_table_is_the_per_block_definition(dtype):
+    x = datagen.column(100_003, dtype, "uniform", seed=31)
+    x[4321] = np.iinfo(x.dtype).min
+    x[99_999] = np.iinfo(x.dtype).max
+    for block in (1, 7, 1000, 65536, 200_000):
+        for op, f in (("sum", lambda v: int(np.sum(v.astype(np.int64)))), ("min", lambda v: int(v.min())),
+                      ("max", lambda v: int(v.max()))):
+            t = oracle.block_table(x, op, block, threads=3)
+            want = [f(x[j:j + block]) for j in range(0, x.size, block)]
+            assert t.tolist() == want, (dtype, block, op)
+
+
+@pytest.mark.parametrize("dtype", ["i32", "i64"])
+def test_range_oracle_equals_whole_slice_oracle(dtype):
+    n = 1_000_003
+    x = datagen.column(n, dtype, "uniform", seed=32)
+    ro = oracle.RangeOracle(x.ctypes.data, n, oracle.DTYPES[dtype], block=4096, threads=4)
+    rng = np.random.default_rng(5)
+    ranges = [(0, 0), (0, n), (5, 1), (4096, 4096), (4095, 2), (4096 * 3 - 1, 4096 * 5 + 2), (n - 17, 17)]
+    for _ in range(40):
+        off = int(rng.integers(0, n))
+        ranges.append((off, int(rng.integers(0, n - off + 1))))
+    for off, m in ranges:
+        for op in ("sum", "min", "max", "count", "avg"):
+            got = ro.aggregate(off, m, op)
+            want = oracle.aggregate(x[off:off + m], op)
+            assert (got.i64, got.count, got.is_null) == (want.i64, want.count, want.is_null), (off, m, op)
+            assert got.f64 == want.f64 or (np.isnan(got.f64) and np.isnan(want.f64)), (off, m, op)
+
+
+def test_range_oracle_wraps_like_the_oracle():
+    x = np.full(300_000, np.iinfo(np.int64).max, dtype=np.int64)
+    ro = oracle.RangeOracle(x.ctypes.data, x.size, oracle.I64, block=1000)
+    for off, m in ((0, 300_000), (17, 123_456)):
+        assert ro.aggregate(off, m, "sum").i64 == oracle.aggregate(x[off:off + m], "sum").i64
+
+
+def test_read_ceiling_reads_every_word():
+    b = np.random.default_rng(3).integers(0, 2 ** 63, size=100_001, dtype=np.int64).view(np.uint64)
+    for threads in (1, 3, 8):
+        assert oracle.read_ceiling(b.ctypes.data, b.nbytes, threads) == int(np.bitwise_xor.reduce(b))
