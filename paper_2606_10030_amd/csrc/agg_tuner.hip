@@ -276,11 +276,8 @@ int agg_tune_load(const char* path) {
   size_t k;
   while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
   std::fclose(f);
-  const std::string dev = device_key();
-  if (dev.empty()) return AGG_E_NODEVICE;
+  // the format first (no device needed), then whether it was written for this device
   if (text.find("\"version\": 1") == std::string::npos) return AGG_E_INVALID;
-  const std::string want = "\"device\": \"" + dev + "\"";
-  if (text.find(want) == std::string::npos) return AGG_E_INVALID;  // another device: ignore
   std::map<Key, Entry> loaded;
   size_t pos = text.find("\"entries\"");
   if (pos == std::string::npos) return AGG_E_INVALID;
@@ -296,6 +293,12 @@ int agg_tune_load(const char* path) {
         !json_num(s, e, "chunk_bytes", &chunk) || !json_num(s, e, "staging_depth", &depth) ||
         !json_num(s, e, "gbs", &gbs))
       return AGG_E_INVALID;
+    // every field an integer in its range before it is converted (NaN fails every comparison)
+    auto whole = [](double v, double lo, double hi) { return v >= lo && v <= hi && v == std::floor(v); };
+    if (!whole(kind, 0, K_NUM - 1) || !whole(src, AGG_SRC_DEVICE, AGG_SRC_ZEROCOPY) || !whole(bucket, 0, 64) ||
+        !whole(w, 1, 16) || !whole(b, 1, 32) || !whole(u, 4, 32) || !whole(nt, 0, 1) ||
+        !whole(chunk, 1 << 20, (double)((int64_t)1 << 32)) || !whole(depth, 2, 4) || !(gbs >= 0.0 && gbs < 1e9))
+      return AGG_E_INVALID;
     agg_tune t;
     t.waves_per_block = (int32_t)w;
     t.blocks_per_cu = (int32_t)b;
@@ -304,10 +307,14 @@ int agg_tune_load(const char* path) {
     t.chunk_bytes = (int64_t)chunk;
     t.staging_depth = (int32_t)depth;
     t.reserved = 0;
-    if ((int)kind < 0 || (int)kind >= K_NUM || !tune_is_valid(t)) return AGG_E_INVALID;
+    if (!tune_is_valid(t)) return AGG_E_INVALID;
     loaded[Key{(int)kind, (int)src, (int)bucket}] = Entry{t, gbs};
     pos = end;
   }
+  const std::string dev = device_key();
+  if (dev.empty()) return AGG_E_NODEVICE;
+  const std::string want = "\"device\": \"" + dev + "\"";
+  if (text.find(want) == std::string::npos) return AGG_E_INVALID;  // another device: ignore
   std::lock_guard<std::mutex> lk(g_tmu);
   for (auto& kv : loaded) g_cache[kv.first] = kv.second;
   return AGG_OK;
