@@ -84,7 +84,10 @@ typedef struct agg_result {   /* 32 bytes */
     int64_t i64;      /* integer SUM / MIN / MAX, COUNT; integer AVG: the SUM */
     double f64;       /* float results, AVG; integer results converted */
     int64_t count;    /* n */
-    int32_t is_null;  /* 1: MIN / MAX / AVG of an empty column */
+    int32_t is_null;  /* 1: MIN / MAX / AVG of an empty column;
+                         -1: agg_run_packed met a corrupt block header (its
+                         payload would lie outside the buffer, or bits > 32):
+                         that block was not read and no other field is valid */
     int32_t prec_used;/* agg_prec for float SUM / AVG, else -1 */
 } agg_result;
 
@@ -333,7 +336,10 @@ int agg_pack_i32(const int32_t* x, int64_t n, agg_packed_block* blocks, uint32_t
  * src is AGG_SRC_DEVICE (blocks and payload in device memory) or
  * AGG_SRC_ZEROCOPY (in page-locked host memory, read by the kernel over PCIe
  * as it decodes).  n <= the plan's max_n.  Enqueues the decoding scan and the
- * combine on `stream`; results equal agg_run on the raw column. */
+ * combine on `stream`; results equal agg_run on the raw column.  The headers
+ * live in memory the host does not read here, so a corrupt one is found by
+ * the kernel: it reads nothing through it and the result comes back with
+ * is_null = -1 (COUNT reads no block and always gives n). */
 int agg_run_packed(agg_plan_t plan, const agg_packed* col, agg_result* out, void* stream);
 
 /* ---- serving: continuous admission of requests (agg_serve) ---- */

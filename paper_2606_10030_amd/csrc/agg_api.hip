@@ -286,6 +286,7 @@ struct agg_plan_s {
   int width = 0;
   void* ws = nullptr;             // segment partial slots
   uint64_t* part = nullptr;
+  uint32_t* err = nullptr;        // packed scans: corrupt-header flag (zero between calls)
   // pinned-host staging
   int depth = 0;
   int64_t stage_bytes = 0;
@@ -348,9 +349,11 @@ int alloc_device(void** p, size_t bytes) { return device_alloc(p, bytes); }
   } while (0)
 
 int plan_create(agg_plan_s* p) {
-  const size_t ws_bytes = (size_t)kSegTarget * 8 * 2;  // segment partials + selected counts
+  // segment partials, selected counts (filtered runs), the packed scan's error word
+  const size_t ws_bytes = (size_t)kSegTarget * 8 * 2 + 256;
   RET_IF(alloc_device(&p->ws, ws_bytes));
   p->part = static_cast<uint64_t*>(p->ws);
+  p->err = reinterpret_cast<uint32_t*>(static_cast<char*>(p->ws) + (size_t)kSegTarget * 8 * 2);
   HIPCHK(hipMemset(p->ws, 0, ws_bytes));
   if (p->src == AGG_SRC_PINNED_HOST) {
     agg_shape s;
@@ -721,7 +724,9 @@ int agg_run_packed(agg_plan_t p, const agg_packed* col, agg_result* out, void* s
   a.nblocks = nblocks;
   a.payload_words = col->payload_words;
   a.part = p->part;
+  a.err = p->err;
   c.nseg = (int64_t)grid * t.waves_per_block;
+  c.err = p->err;
   RET_IF(launch(fn, grid, 64 * t.waves_per_block, &a, stream));
   return launch(comb, 1, kCombineThreads, &c, stream);
 }

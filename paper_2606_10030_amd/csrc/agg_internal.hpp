@@ -37,6 +37,7 @@ struct CombineArgs {
   int64_t n;
   int32_t is_avg;
   int32_t prec_used;
+  uint32_t* err = nullptr;  // packed scans: nonzero if a corrupt block header was seen (read, then cleared)
 };
 
 // One launch of the packed-column scan: each wave folds blocks wave,
@@ -49,6 +50,7 @@ struct PackedArgs {
   int64_t nblocks;
   int64_t payload_words;
   void* part;            // one partial per wave of the launch
+  uint32_t* err;         // set to 1 when a block header is corrupt (the block is not read)
 };
 
 // The range predicate of a filtered scan, as the device sees it: the host

@@ -49,7 +49,14 @@ template <int K>
 __global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
   using P = typename Fold<K>::part;
   const P total = combine_partials<K>(reinterpret_cast<const P*>(a.part), a.nseg);
-  if (threadIdx.x == 0) *a.out = finalize<K>(total, a.n, a.is_avg != 0, a.prec_used);
+  if (threadIdx.x == 0) {
+    agg_result r = finalize<K>(total, a.n, a.is_avg != 0, a.prec_used);
+    if (a.err) {  // a packed column with a corrupt block header: the result is marked invalid
+      if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) r.is_null = -1;
+      __hip_atomic_store(a.err, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // ready for the next call
+    }
+    *a.out = r;
+  }
 }
 
 // ------------------------------------------------------------ packed columns
@@ -112,8 +119,12 @@ __global__ void __launch_bounds__(1024) packed_scan_kernel(PackedArgs a) {
   int32_t ext = K == K_MIN_I32 ? INT32_MAX : INT32_MIN;  // running MIN / MAX
   for (int64_t b = wave; b < a.nblocks; b += nwaves) {
     const agg_packed_block h = a.blocks[b];
-    // a block whose payload would lie outside the buffer is skipped, never read
-    if (h.bits > 32 || h.word_off < 0 || h.word_off + (int64_t)kWave * h.bits > a.payload_words) continue;
+    // a block whose payload would lie outside the buffer is never read; the
+    // result is marked invalid (the combine reads the flag)
+    if (h.bits > 32 || h.word_off < 0 || h.word_off + (int64_t)kWave * h.bits > a.payload_words) {
+      if (lane == 0) __hip_atomic_fetch_or(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      continue;
+    }
     const int64_t left = a.n - b * AGG_PACK_BLOCK;
     const bool full = left >= AGG_PACK_BLOCK;
     int valid = (int)(left - (int64_t)lane * kPerLane);

@@ -57,21 +57,35 @@ def test_packed_sizes_and_partial_blocks(agg, n):
         check(x, "i32", op, "neumaier", got, ctx=f"packed n={n} {op}")
 
 
-def test_corrupt_block_headers_are_skipped_not_read(agg):
+def test_corrupt_block_headers_are_reported_not_read(agg):
+    """A header whose payload lies outside the buffer, or whose width is
+    impossible, is never read through, and the result is marked invalid
+    (is_null = -1; the binding raises); the plan then works normally."""
+    import torch
     x = datagen.column(100_000, "i32", "uniform", seed=5)
     pc = agg.pack_i32(x)
+    good_dev = pc.to("cuda")
     bad = pc.blocks.copy()
     bad[3]["word_off"] = 10**12     # payload offset far outside the buffer
     bad[7]["bits"] = 40             # impossible width
     pc.blocks = bad
     dev = pc.to("cuda")
+    pin = pc.to("pinned")
     got = agg.Plan("i32", "count", max_n=x.size).run_packed(dev)
-    assert got["i64"] == x.size      # COUNT does not read blocks
-    s = agg.Plan("i32", "sum", max_n=x.size).run_packed(dev)
-    keep = np.ones(x.size, bool)
-    keep[3 * 2048:4 * 2048] = False
-    keep[7 * 2048:8 * 2048] = False
-    assert s["i64"] == int(x[keep].astype(np.int64).sum())   # the two bad blocks contribute nothing
+    assert got["i64"] == x.size      # COUNT reads no block
+    for op in ("sum", "min", "max", "avg"):
+        for src, col in (("device", dev), ("zerocopy", pin)):
+            p = agg.Plan("i32", op, max_n=x.size, src=src)
+            with pytest.raises(agg.AggError) as e:
+                p.run_packed(col)
+            assert e.value.code == agg.E_INVALID
+            out = torch.zeros(32, dtype=torch.uint8, device="cuda")
+            p.enqueue_packed(col, out)
+            torch.cuda.synchronize()
+            assert agg.Result.from_buffer_copy(out.cpu().numpy().tobytes()).is_null == -1
+            if src == "device":         # the flag was cleared: the same plan gives the right answer next
+                check(x, "i32", op, "neumaier", p.run_packed(good_dev), ctx=f"after a corrupt column {op}")
+            p.close()
 
 
 def test_packed_rejects_wrong_plans_and_memory(agg):
