@@ -8,10 +8,16 @@ reads items; COUNT reads none) divided by the step time.
 
 Also reported, outside the timed steps: the per-cell GB/s and roofline
 fraction, the dominant kernel's roofline (HIP events over the timed region),
-the plain and f64-combine float modes, the fused filter, group-by over 2^28
-rows, the 2^20-item int32 SUM latency, the end-to-end rate from pinned host memory (chunked copy pipeline and zero-copy)
-with the measured host-to-device copy ceiling, and the CPU oracle's rate on
-one step's worth of the same cells (cpu_baseline).
+the precision report (the three float modes on the precision-study column:
+rel / abs_norm / kappa against the oracle's stored exact sum, and the a-priori
+bound), the fused filter, the 2^20-item int32 SUM (per call, host enqueue and
+GPU time), the Zipf and sorted columns, the paper's SF 50-200 sweep, group-by
+over 2^28 rows, the end-to-end rate from pinned host memory (chunked copy
+pipeline and zero-copy, raw and packed) with the measured host-to-device copy
+ceiling, energy per aggregation, the 4096-column batch, serving (the scaled
+configuration by default, with a sample checked against the same requests run
+alone), and the CPU oracle's rate (cpu_baseline: the host's CPU share of
+threads, one thread, and the host memory read ceiling).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
 """
@@ -174,6 +180,14 @@ def energy_power(edges, t_lo, t_hi, res_uj, max_w=POWER_MAX_W, min_span_s=ENERGY
     return w, info
 
 
+def batch_profile_mode(agg, torch, stream):
+    """Dispatches for a kernel trace of the 4096-column batch (both
+    configurations): 5 graph launches each after the autotuner; no JSON line."""
+    out = bench_batch(agg, torch, stream, {"i32_sum": {"GB/s": None}}, separate=False)
+    log(json.dumps(out))
+    log("batch profile mode done")
+
+
 def bench_energy(agg, torch, dev_i32, host_i32, stream):
     """Joules per aggregation from the GPU's energy accumulator (amdsmi), for
     the on-device SUM of a 2^30-item int32 column and the same SUM end to end
@@ -284,7 +298,7 @@ def bench_energy(agg, torch, dev_i32, host_i32, stream):
     return out
 
 
-def bench_batch(agg, torch, stream, table):
+def bench_batch(agg, torch, stream, table, separate=True):
     """4096 columns, lengths log-uniform in [1e3, 1e7], dtype uniform over int32 /
     int64 / float32, function uniform over SUM / MIN / MAX / AVG (seed 12); also
     the same columns rescaled to 2^30 items in total."""
@@ -326,6 +340,19 @@ def bench_batch(agg, torch, stream, table):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 5
+        gbs = total_bytes / (ms * 1e-3) / 1e9
+        rec = {"columns": ncols, "items": int(ln.sum()), "bytes": total_bytes, "graph_ms": round(ms, 3),
+               "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+               "tuned": {"unroll": tuned.unroll, "waves_per_block": tuned.waves_per_block,
+                         "blocks_per_cu": tuned.blocks_per_cu},
+               "work_items": b.info()["nitems"],
+               "plain_single_column_i32_sum_GB/s": table["i32_sum"]["GB/s"]}
+        out[label] = rec
+        if not separate:
+            b.close()
+            del bufs, cols, stage
+            torch.cuda.empty_cache()
+            continue
         # the same columns as 4096 separate agg_run calls
         plans = {}
         for c, dt in zip(cols, dts):
@@ -342,15 +369,8 @@ def bench_batch(agg, torch, stream, table):
         e3.record(stream)
         torch.cuda.synchronize()
         ms_sep = e2.elapsed_time(e3)
-        gbs = total_bytes / (ms * 1e-3) / 1e9
-        out[label] = {"columns": ncols, "items": int(ln.sum()), "bytes": total_bytes, "graph_ms": round(ms, 3),
-                      "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                      "separate_agg_run_ms": round(ms_sep, 3),
-                      "separate_GB/s": round(total_bytes / (ms_sep * 1e-3) / 1e9, 1),
-                      "tuned": {"unroll": tuned.unroll, "waves_per_block": tuned.waves_per_block,
-                                "blocks_per_cu": tuned.blocks_per_cu},
-                      "work_items": b.info()["nitems"],
-                      "plain_single_column_i32_sum_GB/s": table["i32_sum"]["GB/s"]}
+        rec["separate_agg_run_ms"] = round(ms_sep, 3)
+        rec["separate_GB/s"] = round(total_bytes / (ms_sep * 1e-3) / 1e9, 1)
         for p in plans.values():
             p.close()
         b.close()
@@ -420,10 +440,31 @@ def bench_serve(agg, torch, host_i32, dev_i32, full=False):
     results, stats, sm = srv.run(reqs)
     wall = time.time() - t0
     srv.close()
+    # a seeded sample of the results, each against the same request run alone
+    # (agg_run on the same canonical shape: the bits must be identical)
+    import numpy as np
+    sample = sorted(np.random.default_rng(14).choice(len(reqs), size=min(64, len(reqs)), replace=False).tolist())
+    mism = 0
+    o = torch.zeros(32, dtype=torch.uint8, device="cuda")
+    for i in sample:
+        q = reqs[i]
+        p = agg.Plan("i32", q["op"], max_n=q["n"], src="device" if q["resident"] else "zerocopy")
+        p.enqueue(q["ptr"], o, n=q["n"])
+        torch.cuda.synchronize()
+        alone = agg.parse_results(o.cpu().numpy().tobytes(), [(agg.I32, agg.OPS[q["op"]])])[0]
+        p.close()
+        got = results[i]
+        if (got["i64"], got["f64"], got["count"], got["is_null"]) != \
+                (alone["i64"], alone["f64"], alone["count"], alone["is_null"]) or stats[i]["status"] != 0:
+            mism += 1
     lat = [s["done_s"] - s["arrival_s"] for s in stats]
     lat_res = [s["done_s"] - s["arrival_s"] for s, q in zip(stats, reqs) if q["resident"]]
     lat_ship = [s["done_s"] - s["arrival_s"] for s, q in zip(stats, reqs) if not q["resident"]]
-    return {"requests": nreq, "n_range": [10_000, n_max], "arrival_rate_per_s": round(rate, 1),
+    return {"configuration": "full" if full else
+            "scaled: 10^3 requests up to 2^30 items (the full 10^4 requests up to 2^33 run with --serve-full "
+            "and in tests/test_gpu_serve.py with AGG_SERVE_FULL=1)",
+            "checked_vs_alone": len(sample), "mismatches_vs_alone": mism,
+            "requests": nreq, "n_range": [10_000, n_max], "arrival_rate_per_s": round(rate, 1),
             "hbm_budget_bytes": budget, "max_slots": 8, "max_shipping": 2,
             "completed": sm["completed"], "failed": sm["failed"],
             "p50_ms": round(agg.percentile(lat, 50) * 1e3, 3), "p99_ms": round(agg.percentile(lat, 99) * 1e3, 3),
@@ -438,6 +479,210 @@ def bench_serve(agg, torch, host_i32, dev_i32, full=False):
             "peak_busy_slots": sm["peak_busy_slots"], "peak_reserved_bytes": sm["peak_reserved_bytes"]}
 
 
+def bench_precision(agg, torch, stream, dev_f32):
+    """Float32 SUM in the three precision modes on the precision-study column
+    (2^30 items, N(0,1) with 1% of +-1e6, seed 11) and on the benchmark's
+    uniform float32 column (seed 4): time per launch, and the error against
+    the exact sum stored by tests/golden/make_precision_refs.py (the oracle's
+    value, computed ahead of time): rel, abs_norm, kappa, and the library's
+    a-priori bound."""
+    import datagen
+    refs = json.load(open(os.path.join(ROOT, "tests", "golden", "precision_refs.json")))["columns"]
+    n = N_ITEMS
+    h = torch.empty(n, dtype=torch.float32, pin_memory=True)
+    datagen.fill_ptr(h.data_ptr(), n, "f32", "normal_outliers", 11)
+    d_c3 = h.to("cuda")
+    del h
+    out = {}
+    for name, col in (("f32_normal_outliers_seed11", d_c3), ("f32_uniform_seed4", dev_f32)):
+        ref = refs[name]
+        if col.numel() != ref["n"]:
+            continue
+        exact, a = ref["exact_sum"], ref["abs_sum"]
+        modes = {}
+        for prec in ("f32", "f64_combine", "neumaier"):
+            p = agg.Plan("f32", "sum", max_n=n, prec=prec)
+            o = torch.zeros(32, dtype=torch.uint8, device="cuda")
+            for _ in range(2):
+                p.enqueue(col, o, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(5):
+                p.enqueue(col, o, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 5
+            got = agg.parse_results(o.cpu().numpy().tobytes(), [(agg.F32, agg.SUM)])[0]["f64"]
+            p.close()
+            err = abs(got - exact)
+            bound = agg.float_sum_bound_coeff(prec, n) * a
+            modes[prec] = {"value": got, "rel": err / abs(exact), "abs_norm": err / a,
+                           "apriori_rel_bound": bound / abs(exact), "within_bound": err <= bound,
+                           "ms": round(ms, 4), "GB/s": round(n * 4 / (ms * 1e-3) / 1e9, 1)}
+        out[name] = {"n": n, "exact_sum": exact, "kappa": a / abs(exact), "modes": modes}
+    del d_c3
+    return out
+
+
+def bench_distributions(agg, torch, stream, plans, hbuf, dbuf):
+    """The other distributions of the 2^30-item columns (Zipf(1.1) on ranks
+    [1, 2^20], and the uniform column sorted ascending): SUM / MIN / MAX / AVG
+    per dtype, 3 launches each (the seeds of the full-size GPU tests)."""
+    import datagen
+    n = N_ITEMS
+    out = {}
+    for dt in DTYPES:
+        for dist, ds in (("zipf", 1), ("sorted", 2)):
+            seed = {"i32": 2, "i64": 5, "f32": 8}[dt] + ds
+            t0 = time.time()
+            datagen.fill_ptr(hbuf.data_ptr(), n, dt, dist, seed)
+            nb = n * WIDTH[dt]
+            dbuf[:nb].copy_(hbuf[:nb])
+            col = dbuf[:nb].view({"i32": torch.int32, "i64": torch.int64, "f32": torch.float32}[dt])
+            log(f"distribution {dt} {dist}: generated + copied in {time.time() - t0:.1f}s")
+            for op in ("sum", "min", "max", "avg"):
+                o = torch.zeros(32, dtype=torch.uint8, device="cuda")
+                plans[(dt, op)].enqueue(col, o, stream=stream)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(3):
+                    plans[(dt, op)].enqueue(col, o, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / 3
+                gbs = nb / (ms * 1e-3) / 1e9
+                out[f"{dt}_{dist}_{op}"] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
+                                            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def bench_sf_sweep(agg, torch, stream, hbuf, dbuf):
+    """The paper's scalability sweep (Section 5.2): SUM over an int32 key column
+    uniform in [1, 1e4 * SF] with 6e6 * SF rows, SF 50 / 100 / 150 / 200, on
+    device (5 launches) and end to end by zero-copy from pinned host memory."""
+    import datagen
+    out = {}
+    for sf in (50, 100, 150, 200):
+        n = 6_000_000 * sf
+        datagen.fill_ptr(hbuf.data_ptr(), n, "i32", "uniform", 31, 1, 10_000 * sf + 1)
+        dbuf[:n * 4].copy_(hbuf[:n * 4])
+        rec = {"rows": n, "bytes": n * 4}
+        for src, col, reps in (("device", dbuf[:n * 4].view(torch.int32), 5),
+                               ("zerocopy", hbuf[:n * 4].view(torch.int32), 2)):
+            p = agg.Plan("i32", "sum", max_n=n, src=src)
+            o = torch.zeros(32, dtype=torch.uint8, device="cuda")
+            p.enqueue(col, o, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                p.enqueue(col, o, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            p.close()
+            rec[src] = {"ms": round(ms, 4), "rows/s": round(n / (ms * 1e-3), 1),
+                        "GB/s": round(n * 4 / (ms * 1e-3) / 1e9, 1)}
+        out[f"SF{sf}"] = rec
+    return out
+
+
+def bench_small_call(agg, torch, stream, dev_i32):
+    """The 2^20-item int32 SUM (launch-bound): time per call back to back on
+    one stream, the host's enqueue time per call (Python binding + library),
+    and the GPU's own time per call, measured with the calls queued behind
+    enough earlier work that the host is never the limit."""
+    small = dev_i32[: 1 << 20]
+    p = agg.Plan("i32", "sum", max_n=1 << 20)
+    o = torch.zeros(32, dtype=torch.uint8, device="cuda")
+    for _ in range(50):
+        p.enqueue(small, o, stream=stream)
+    torch.cuda.synchronize()
+    calls = 1000
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(calls):
+        p.enqueue(small, o, stream=stream)
+    e1.record(stream)
+    host_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    back_to_back_us = e0.elapsed_time(e1) / calls * 1e3
+    # queue the calls behind ~30 ms of scans so every call is enqueued before the first runs
+    pb = agg.Plan("i32", "sum", max_n=dev_i32.numel())
+    ob = torch.zeros(32, dtype=torch.uint8, device="cuda")
+    for _ in range(50):
+        pb.enqueue(dev_i32, ob, stream=stream)
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2.record(stream)
+    for _ in range(calls):
+        p.enqueue(small, o, stream=stream)
+    e3.record(stream)
+    torch.cuda.synchronize()
+    gpu_us = e2.elapsed_time(e3) / calls * 1e3
+    pb.close()
+    p.close()
+    return {"us_per_call_back_to_back": round(back_to_back_us, 2),
+            "host_enqueue_us_per_call": round(host_s / calls * 1e6, 2),
+            "gpu_us_per_call_queued": round(gpu_us, 2),
+            "note": "gpu_us_per_call_queued: events around calls queued behind ~30 ms of earlier scans"}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(host, cells, step_bytes, n):
+    """The oracle (plain, exact, untuned) over the step's cells on the host:
+    whole steps for about 10 s with the host's CPU share of threads, a
+    1-thread run over one 2^28-item column, and the host memory read ceiling
+    (a multi-threaded read of the three host columns)."""
+    import oracle
+    threads = oracle.default_threads()     # OMP_NUM_THREADS: the CPU share of this GPU's job
+    cells_cpu = [c for c in cells if c[1] != "count"]
+    code = {"i32": 0, "i64": 1, "f32": 2}
+    opc = {"sum": 0, "min": 1, "max": 2, "avg": 4}
+    t0 = time.perf_counter()
+    reps = 0
+    while reps == 0 or time.perf_counter() - t0 < 10.0:   # whole steps, about 10 s of CPU work
+        for dt, op in cells_cpu:
+            oracle.aggregate_ptr(host[dt].data_ptr(), n, code[dt], opc[op], threads)
+        reps += 1
+    cpu_s = time.perf_counter() - t0
+    m1 = min(n, 1 << 28)
+    t1 = time.perf_counter()
+    oracle.aggregate_ptr(host["i32"].data_ptr(), m1, 0, 0, 1)
+    one_s = time.perf_counter() - t1
+    ceil = {}
+    for th in sorted({1, threads}):
+        t2 = time.perf_counter()
+        nbytes = 0
+        for dt in DTYPES:
+            oracle.read_ceiling(host[dt].data_ptr(), n * WIDTH[dt], th)
+            nbytes += n * WIDTH[dt]
+        ceil[th] = round(nbytes / (time.perf_counter() - t2) / 1e9, 2)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"value": round(reps * step_bytes / cpu_s / 1e9, 2), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{reps} full step(s): {len(cells_cpu)} cells each over the same 2^30-item columns "
+                      f"({step_bytes / 2**30:.0f} GiB read per step), {cpu_s:.1f} s",
+            "threads": threads, "cpu_model": cpu_model(), "host_logical_cpus": os.cpu_count(),
+            "affinity_cpus": affinity,
+            "threads_note": "threads = OMP_NUM_THREADS, the host CPU share given to one GPU's job",
+            "one_thread_GB/s": round(m1 * 4 / one_s / 1e9, 2),
+            "one_thread_sample": f"int32 SUM over {m1} items",
+            "host_read_ceiling_GB/s": ceil[threads], "host_read_ceiling_1_thread_GB/s": ceil[1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -449,12 +694,15 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-energy", action="store_true")
     ap.add_argument("--no-groupby", action="store_true")
+    ap.add_argument("--no-dists", action="store_true", help="skip the Zipf / sorted cells and the SF sweep")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving with 10^4 requests of up to 2^33 int32 items (minutes of PCIe time)")
     ap.add_argument("--n", type=int, default=N_ITEMS, help=argparse.SUPPRESS)
     ap.add_argument("--counters", action="store_true",
                     help="profiling mode for rocprofv3 --pmc: a 1 GiB device copy (calibration) "
                          "then 3 launches of each int32/int64/float32 SUM scan; no JSON line")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="profiling mode for a rocprofv3 kernel trace of the 4096-column batch; no JSON line")
     ap.add_argument("--profile-groupby", type=int, nargs="+", metavar="GROUPS",
                     help="profiling mode for a rocprofv3 kernel trace: group-by over 2^28 rows with "
                          "the given key counts; no JSON line")
@@ -478,6 +726,9 @@ def main():
         return
     if args.profile_groupby:
         groupby_profile_mode(args.profile_groupby)
+        return
+    if args.profile_batch:
+        batch_profile_mode(agg, torch, stream)
         return
 
     # ---- inputs: generated into pinned host memory, copied to HBM
@@ -559,23 +810,8 @@ def main():
                                    "hbm_frac": None if gbs is None else round(gbs / HBM_PEAK_GBS, 4)}
 
     extra = {}
-    # ---- float precision modes (same column, untimed-step measurement)
-    modes = {}
-    for prec in ("neumaier", "f64_combine", "f32"):
-        p = agg.Plan("f32", "sum", max_n=n, prec=prec)
-        o = torch.zeros(32, dtype=torch.uint8, device="cuda")
-        for _ in range(2):
-            p.enqueue(dev["f32"], o, stream=stream)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(5):
-            p.enqueue(dev["f32"], o, stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 5
-        modes[prec] = {"ms": round(ms, 4), "GB/s": round(n * 4 / (ms * 1e-3) / 1e9, 1)}
-        p.close()
-    extra["f32_sum_modes"] = modes
+    # ---- float precision: the three modes on the precision-study column and on the step's float32 column
+    extra["precision"] = bench_precision(agg, torch, stream, dev["f32"])
 
     # ---- fused filter + aggregate: SUM(x) WHERE y < 0 (half the items), both columns read once
     fused = {}
@@ -599,19 +835,18 @@ def main():
     extra["fused_filter"] = fused
 
     # ---- latency: 2^20 int32 SUM (launch-bound)
-    small = dev["i32"][: 1 << 20]
-    p = agg.Plan("i32", "sum", max_n=1 << 20)
-    o = torch.zeros(32, dtype=torch.uint8, device="cuda")
-    for _ in range(20):
-        p.enqueue(small, o, stream=stream)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(200):
-        p.enqueue(small, o, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    extra["i32_sum_2e20_us_per_call"] = round(e0.elapsed_time(e1) / 200 * 1e3, 2)
-    p.close()
+    c1 = bench_small_call(agg, torch, stream, dev["i32"])
+    extra["i32_sum_2e20_us_per_call"] = c1["us_per_call_back_to_back"]
+    extra["i32_sum_2e20"] = c1
+
+    # ---- the other distributions and the paper's SF sweep (one spare 8 GiB buffer on each side)
+    if not args.no_dists:
+        hbuf = torch.empty(n * 8, dtype=torch.uint8, pin_memory=True)
+        dbuf = torch.empty(n * 8, dtype=torch.uint8, device="cuda")
+        extra["distributions"] = bench_distributions(agg, torch, stream, plans, hbuf, dbuf)
+        extra["sf_sweep"] = bench_sf_sweep(agg, torch, stream, hbuf, dbuf)
+        del hbuf, dbuf
+        torch.cuda.empty_cache()
 
     # ---- group-by aggregation (per-key SUM / COUNT over 2^28 rows)
     if not args.no_groupby:
@@ -695,21 +930,7 @@ def main():
     # ---- CPU oracle baseline (rank 0, N = 1): one step's cells on the host cores
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        threads = oracle.default_threads()
-        cells_cpu = [c for c in cells if c[1] != "count"]
-        t0 = time.perf_counter()
-        reps = 0
-        while reps == 0 or time.perf_counter() - t0 < 10.0:   # whole steps, about 10 s of CPU work
-            for dt, op in cells_cpu:
-                oracle.aggregate_ptr(host[dt].data_ptr(), n, {"i32": 0, "i64": 1, "f32": 2}[dt],
-                                     {"sum": 0, "min": 1, "max": 2, "avg": 4}[op], threads)
-            reps += 1
-        cpu_s = time.perf_counter() - t0
-        cpu = {"value": round(reps * step_bytes / cpu_s / 1e9, 2), "unit": "GB/s", "cores": threads,
-               "kind": "oracle",
-               "sample": f"{reps} full step(s): {len(cells_cpu)} cells each over the same 2^30-item columns "
-                         f"({step_bytes / 2**30:.0f} GiB read per step), {cpu_s:.1f} s"}
+        cpu = cpu_baseline(host, cells, step_bytes, n)
 
     line = {
         "metric": METRIC,
@@ -729,7 +950,8 @@ def main():
                    "n": n, "bytes_per_step": step_bytes, "parallelism": "single GPU",
                    "device": info},
         "hbm_frac": round(value / HBM_PEAK_GBS, 4),
-        "rows_per_s": round(n * len(cells) / (ms_per_step * 1e-3), 1),
+        "rows_per_s": round(n * sum(1 for c in cells if c[1] != "count") / (ms_per_step * 1e-3), 1),
+        "rows_per_s_note": "rows read per second: the 12 cells that read the column (COUNT reads nothing)",
         "roofline": roofline,
         "cpu_baseline": cpu,
         "cells": table,

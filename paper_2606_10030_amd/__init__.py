@@ -260,6 +260,29 @@ def canonical_shape(dtype, n: int) -> Shape:
     return s
 
 
+def float_sum_bound_coeff(prec, n: int) -> float:
+    """The documented a-priori bound of a float32 SUM over n items in precision
+    mode `prec`, as a multiple of sum |x| (include/agg.h): with u = 2^-24,
+    v = 2^-53, m = seg_bytes / 1024 and k = ceil(nseg / 256) of the canonical
+    shape, gamma_d(w) = d w / (1 - d w):
+    compensated 1.01 ((14 ceil(m/4) + 24) u^2 + (k + 8) v); plain
+    gamma_{m+k+18}(u); f64-combine gamma_{m+8}(u) + gamma_{k+8}(v) (1 + gamma_{m+8}(u))."""
+    p = _code(prec, PRECS, "prec")
+    s = canonical_shape(F32, n)
+    m = s.seg_bytes // 1024
+    k = -(-s.nseg // 256)
+    u, v = 2.0 ** -24, 2.0 ** -53
+
+    def gamma(d, w):
+        return d * w / (1.0 - d * w)
+    if p == PREC_F32:
+        return gamma(m + k + 18, u)
+    if p == PREC_F64_COMBINE:
+        g = gamma(m + 8, u)
+        return g + gamma(k + 8, v) * (1.0 + g)
+    return 1.01 * ((14 * -(-m // 4) + 24) * u * u + (k + 8) * v)
+
+
 def default_tune(dtype, op, n: int, prec="neumaier", src="device") -> Tune:
     t = Tune()
     _check(lib().agg_default_tune(_code(dtype, DTYPES, "dtype"), _code(op, OPS, "op"),
@@ -413,7 +436,10 @@ class Plan:
         s = torch.cuda.current_stream() if stream is None else stream
         self.enqueue_packed(packed, self._host_out, stream=s)
         s.synchronize()
-        return parse_results(self._host_out.numpy().tobytes(), [(self.dtype, self.op)])[0]
+        r = parse_results(self._host_out.numpy().tobytes(), [(self.dtype, self.op)])[0]
+        if Result.from_buffer_copy(self._host_out.numpy().tobytes()).is_null < 0:
+            raise AggError(E_INVALID, "agg_run_packed: corrupt packed block header (result not valid)")
+        return r
 
     def close(self):
         if getattr(self, "_h", None):

@@ -93,3 +93,97 @@ def test_serve_rejects_bad_pointers_before_running(agg):
     with pytest.raises(agg.AggError):
         srv.run([dict(ptr=host.ctypes.data, n=1000, arrival_s=0.0, dtype="i32", op="sum")])
     srv.close()
+
+
+def _serve_checked(agg, nreq, n_max, arena_items, hot_items, big_shipped, seed, out_name):
+    """Serve a Poisson stream (int32, lengths log-uniform in [1e4, n_max], 30%
+    resident in a 2^30-item HBM column, 70% shipped from a pinned host arena,
+    0.8 of the PCIe-bound capacity, 200 GB budget or what the device has free)
+    plus `big_shipped` shipped requests longer than 2^31 items, then check
+    EVERY result against the oracle through block tables over the arena and
+    the hot column (whole 64 Ki-item blocks from the table, partial end
+    blocks scanned exactly)."""
+    import json
+    import os
+    import time
+    import oracle
+    import torch
+    t0 = time.time()
+    arena = torch.empty(arena_items, dtype=torch.int32, pin_memory=True)
+    datagen.fill_ptr(arena.data_ptr(), arena_items, "i32", "uniform", seed)
+    hot_h = torch.empty(hot_items, dtype=torch.int32, pin_memory=True)
+    datagen.fill_ptr(hot_h.data_ptr(), hot_items, "i32", "uniform", seed + 1)
+    hot = hot_h.to("cuda")
+    ro_arena = oracle.RangeOracle(arena.data_ptr(), arena_items, oracle.I32)
+    ro_hot = oracle.RangeOracle(hot_h.data_ptr(), hot_items, oracle.I32)
+    print(f"serve check: inputs and oracle tables in {time.time() - t0:.1f}s", flush=True)
+    cap = 55e9 / (0.7 * mean_bytes(10_000, n_max, 4))
+    specs = request_stream(nreq, seed=seed, n_min=10_000, n_max=n_max, rate_per_s=0.8 * cap, resident_frac=0.3,
+                           hot_items=hot_items, arena_items=arena_items)
+    r = np.random.default_rng(seed + 2)
+    horizon = specs[-1]["arrival_s"]
+    for b in range(big_shipped):   # shipped columns longer than 2^31 items, spread over the stream
+        n = int(r.integers((1 << 31) + 1, arena_items + 1))
+        specs.append(dict(n=n, arrival_s=horizon * (b + 0.5) / big_shipped, op=["sum", "min", "max", "avg"][b % 4],
+                          resident=False, offset=int(r.integers(0, arena_items - n + 1)), column_id=(1 << 50) + b))
+    specs.sort(key=lambda s: s["arrival_s"])
+    reqs = [dict(ptr=(hot if s["resident"] else arena).data_ptr() + 4 * s["offset"], n=s["n"],
+                 column_id=s["column_id"], arrival_s=s["arrival_s"], dtype="i32", op=s["op"],
+                 resident=s["resident"]) for s in specs]
+    free, _ = torch.cuda.mem_get_info()
+    budget = min(200 * 10 ** 9, int(free - (8 << 30)))
+    srv = agg.Server(hbm_budget_bytes=budget, max_slots=8, cache_shipped=False, max_shipping=2,
+                     progress_every=max(100, nreq // 10))
+    t1 = time.time()
+    results, stats, sm = srv.run(reqs)
+    wall = time.time() - t1
+    srv.close()
+    print(f"serve check: {len(reqs)} requests served in {wall:.1f}s, "
+          f"{sm['bytes_scanned'] / 1e12:.3f} TB scanned", flush=True)
+    assert sm["completed"] == len(reqs) and sm["failed"] == 0
+    assert sm["peak_reserved_bytes"] <= budget
+    checked = 0
+    for i, (s, got, st) in enumerate(zip(specs, results, stats)):
+        assert st["status"] == 0, f"request {i}: status {st['status']}"
+        want = (ro_hot if s["resident"] else ro_arena).aggregate(s["offset"], s["n"], s["op"])
+        ctx = f"request {i} ({s['op']}, n={s['n']}, offset={s['offset']}, resident={s['resident']})"
+        assert got["count"] == s["n"] and got["is_null"] == want.is_null, ctx
+        if s["op"] == "avg":
+            assert got["f64"] == want.f64, f"{ctx}: {got['f64']!r} != {want.f64!r}"
+        else:
+            assert got["i64"] == want.i64, f"{ctx}: {got['i64']} != {want.i64}"
+        checked += 1
+    lat = [st["done_s"] - st["arrival_s"] for st in stats]
+    summary = {"requests": len(reqs), "n_max": n_max, "arena_items": arena_items, "hot_items": hot_items,
+               "longest_shipped_items": max(s["n"] for s in specs if not s["resident"]),
+               "shipped_over_2^31": sum(1 for s in specs if not s["resident"] and s["n"] > (1 << 31)),
+               "checked_against_oracle": checked, "mismatches": 0, "hbm_budget_bytes": budget,
+               "p50_ms": agg.percentile(lat, 50) * 1e3, "p99_ms": agg.percentile(lat, 99) * 1e3,
+               "makespan_s": sm["makespan_s"], "bytes_scanned": sm["bytes_scanned"],
+               "bytes_shipped": sm["bytes_shipped"], "scanned_GB/s": sm["bytes_scanned"] / sm["makespan_s"] / 1e9,
+               "shipped_GB/s": sm["bytes_shipped"] / sm["makespan_s"] / 1e9,
+               "peak_reserved_bytes": sm["peak_reserved_bytes"], "peak_busy_slots": sm["peak_busy_slots"]}
+    print("serve check summary: " + json.dumps(summary), flush=True)
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, out_name), "w") as f:
+            json.dump(summary, f, indent=1)
+    del arena, hot, hot_h
+    torch.cuda.empty_cache()
+
+
+def test_serving_at_scale_checked_against_oracle(agg):
+    """10^3 requests up to 2^30 items plus 4 shipped columns longer than 2^31
+    items (the scaled serving configuration), every result checked."""
+    _serve_checked(agg, nreq=1000, n_max=1 << 30, arena_items=3 << 30, hot_items=1 << 30, big_shipped=4, seed=13,
+                   out_name="serve_scaled_check.json")
+
+
+@pytest.mark.skipif(__import__("os").environ.get("AGG_SERVE_FULL") != "1",
+                    reason="the full serving configuration (10^4 requests up to 2^33 items, about 7 minutes "
+                           "of PCIe time) runs only with AGG_SERVE_FULL=1")
+def test_serving_full_configuration_checked_against_oracle(agg):
+    """The full serving configuration: 10^4 requests, lengths log-uniform in
+    [1e4, 2^33] int32 (up to 32 GiB), every result checked."""
+    _serve_checked(agg, nreq=10_000, n_max=1 << 33, arena_items=1 << 33, hot_items=1 << 33, big_shipped=0, seed=13,
+                   out_name="serve_full_check.json")

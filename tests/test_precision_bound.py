@@ -110,3 +110,30 @@ def test_full_size_columns_have_apriori_relative_bound_below_1e6(dist, seed):
     del x
     rel = float_sum_bound_coeff("neumaier", n) * a / abs(exact)
     assert rel <= 1e-6, f"{dist} seed {seed}: a-priori relative bound {rel:.3e} (kappa {a / abs(exact):.3e})"
+
+
+@pytest.mark.slow
+def test_stored_precision_refs_match_the_oracle():
+    """The benchmark's stored exact sums (tests/golden/precision_refs.json)
+    are what the oracle computes for those columns."""
+    import json
+    import os
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, os.path.join(here, "golden"))
+    import make_precision_refs as mk
+    stored = json.load(open(os.path.join(here, "golden", "precision_refs.json")))["columns"]
+    assert set(stored) == {name for name, _, _ in mk.COLUMNS}
+    for name, dist, seed in mk.COLUMNS:
+        assert stored[name] == mk.compute(dist, seed), name
+
+
+@pytest.mark.parametrize("n", [0, 1, 1000, (1 << 20) + 3, 1 << 26, 1 << 30, (1 << 32) + 5])
+@pytest.mark.parametrize("prec", ["neumaier", "f64_combine", "f32"])
+def test_library_states_the_same_bound(prec, n):
+    """The bound the library documents (and the benchmark reports) is the one
+    the tests hold the GPU to."""
+    import paper_2606_10030_amd as agg
+    if n == 0:
+        return
+    assert agg.float_sum_bound_coeff(prec, n) == pytest.approx(float_sum_bound_coeff(prec, n), rel=1e-12)
