@@ -173,6 +173,24 @@ int agg_plan(agg_plan_t* out, int32_t dtype, int32_t op, int32_t prec, int64_t m
  * may be captured into a HIP graph (DEVICE, ZEROCOPY). */
 int agg_run(agg_plan_t plan, const void* col, int64_t n, agg_result* out, void* stream);
 
+/* agg_run without a plan, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * it allocates nothing, on the device or the host.  The segment partials live
+ * in a 64 KiB array in the library's device code, one per device (held until
+ * the process ends; agg_init sets it up, else the first call on a device).
+ * Same kernels, canonical shape and result bits as agg_run with a plan of the
+ * same (dtype, op, prec); launch parameters from agg_default_tune.
+ *   src: AGG_SRC_DEVICE or AGG_SRC_ZEROCOPY (PINNED_HOST would need a staging
+ *        ring, so it is AGG_E_INVALID);
+ *   col, n, out: as for agg_run; n <= 2^40 (any such column fits the array).
+ * All calls on one device share its array: two calls that overlap in time on
+ * that device (two streams, two threads) race and give wrong results;
+ * serialise them (for instance on one stream).  Returns AGG_E_INVALID for bad
+ * arguments, AGG_E_NODEVICE without a gfx950 device, AGG_E_HIP if the array's
+ * address cannot be obtained. */
+int agg_run_noalloc(int32_t dtype, int32_t op, int32_t prec, int32_t src, const void* col, int64_t n,
+                    agg_result* out, void* stream);
+
 /* The canonical shape and launch parameters the plan uses for n items. */
 int agg_plan_info(agg_plan_t plan, int64_t n, agg_shape* shape, agg_tune* tune);
 

@@ -159,6 +159,7 @@ def lib():
         "agg_default_tune": ([i32, i32, i32, i64, i32, ctypes.POINTER(Tune)], ctypes.c_int),
         "agg_plan": ([ctypes.POINTER(vp), i32, i32, i32, i64, i32, ctypes.POINTER(Tune)], ctypes.c_int),
         "agg_run": ([vp, vp, i64, vp, vp], ctypes.c_int),
+        "agg_run_noalloc": ([i32, i32, i32, i32, vp, i64, vp, vp], ctypes.c_int),
         "agg_plan_info": ([vp, i64, ctypes.POINTER(Shape), ctypes.POINTER(Tune)], ctypes.c_int),
         "agg_plan_destroy": ([vp], ctypes.c_int),
         "agg_batch_plan": ([ctypes.POINTER(vp), ctypes.POINTER(Col), i32, ctypes.POINTER(Tune)], ctypes.c_int),

@@ -276,6 +276,11 @@ int launch(const void* fn, int grid, int block, void* args, hipStream_t stream) 
 
 }  // namespace agg
 
+// The no-allocation entry point's segment partials (agg_run_noalloc): 64 KiB,
+// the partials of any canonical shape (at most kSegTarget segments).
+constexpr int64_t kScratchSlots = kSegTarget;
+static __device__ __align__(256) uint64_t scratch[kScratchSlots];
+
 struct agg_plan_s {
   int device = 0;
   int32_t dtype = 0, op = 0, prec = 0, src = 0;
@@ -419,11 +424,81 @@ int batch_capture(agg_batch_s* b, const agg_tune& t) {
   return AGG_OK;
 }
 
+// The scan of a column the kernels can read directly (device memory, or
+// page-locked host memory read over PCIe) and the combine, with `part` as
+// the segment-partial scratch (kSegTarget 8-byte slots).  Shared by agg_run
+// and agg_run_noalloc; the caller has validated everything.
+int enqueue_resident(int kind, int32_t dtype, int32_t op, int32_t prec, const agg_tune& t, int cu, const void* col,
+                     int64_t n, agg_result* out, uint64_t* part, hipStream_t stream) {
+  agg_shape s;
+  shape_of(dtype, n, &s);
+  const bool is_float_sum = dtype == AGG_F32 && (op == AGG_SUM || op == AGG_AVG);
+  CombineArgs c;
+  c.part = part;
+  c.nseg = s.nseg;
+  c.out = out;
+  c.n = n;
+  c.is_avg = op == AGG_AVG;
+  c.prec_used = is_float_sum ? prec : -1;
+  const void* combine_fn = combine_kernel_ptr(kind);
+  if (!combine_fn) return AGG_E_INVALID;
+  if (s.nseg > 0) {
+    const bool aligned = (reinterpret_cast<uintptr_t>(col) & 15) == 0;
+    const void* fn = scan_kernel_ptr(kind, t.unroll, t.nontemporal != 0, aligned);
+    if (!fn) return AGG_E_INVALID;
+    ScanArgs a;
+    a.base = static_cast<const char*>(col);
+    a.col_bytes = n * width_of(dtype);
+    a.seg_bytes = s.seg_bytes;
+    a.seg_lo = 0;
+    a.seg_hi = s.nseg;
+    a.base_seg = 0;
+    a.part = part;
+    RET_IF(launch(fn, grid_for(t, cu, s.nseg), 64 * t.waves_per_block, &a, stream));
+  }
+  return launch(combine_fn, 1, kCombineThreads, &c, stream);
+}
+
+// ------------------------------------------------------------ no-allocation scratch
+// agg_run_noalloc's segment partials: one array per device, in the library's
+// own device code (each device holds its copy until the process ends).  Its
+// name is only a host-side stand-in; host code uses the address that
+// hipGetSymbolAddress returns on each device, looked up once per device with
+// that device current.
+uint64_t* g_scratch[kMaxDevices] = {};
+
+// The device's scratch address (dev must be current).
+int scratch_of(int dev, uint64_t** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      g_last_hip = (int32_t)(e != hipSuccess ? e : hipErrorInvalidSymbol);
+      return AGG_E_HIP;
+    }
+    g_scratch[dev] = static_cast<uint64_t*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return AGG_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int agg_init(int32_t device) { return device_check(device); }
+int agg_init(int32_t device) {
+  RET_IF(device_check(device));
+  // set up the no-allocation scratch of this device, with the device current
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != device) HIPCHK(hipSetDevice(device));
+  uint64_t* sp = nullptr;
+  const int rc = scratch_of(device, &sp);
+  if (cur != device) HIPCHK(hipSetDevice(cur));
+  return rc;
+}
 
 int agg_device_info(int32_t device, int32_t* cu_count, char* arch, int32_t arch_len) {
   const int rc = device_check(device);
@@ -501,7 +576,6 @@ int agg_run(agg_plan_t p, const void* col, int64_t n, agg_result* out, void* str
   RET_IF(check_out_pointer(out, sizeof(agg_result), p->device));
   const agg_tune& t = p->tune;
   const int cu = g_dev[p->device].cu;
-  const bool aligned = (reinterpret_cast<uintptr_t>(col) & 15) == 0;
   const bool is_float_sum = p->dtype == AGG_F32 && (p->op == AGG_SUM || p->op == AGG_AVG);
 
   ScanArgs a;
@@ -518,18 +592,8 @@ int agg_run(agg_plan_t p, const void* col, int64_t n, agg_result* out, void* str
   const void* combine_fn = combine_kernel_ptr(p->kind);
   if (!combine_fn) return AGG_E_INVALID;
 
-  if (p->src != AGG_SRC_PINNED_HOST || n == 0) {
-    if (s.nseg > 0) {
-      const void* fn = scan_kernel_ptr(p->kind, t.unroll, t.nontemporal != 0, aligned);
-      if (!fn) return AGG_E_INVALID;
-      a.base = static_cast<const char*>(col);
-      a.seg_lo = 0;
-      a.seg_hi = s.nseg;
-      a.base_seg = 0;
-      RET_IF(launch(fn, grid_for(t, cu, s.nseg), 64 * t.waves_per_block, &a, stream));
-    }
-    return launch(combine_fn, 1, kCombineThreads, &c, stream);
-  }
+  if (p->src != AGG_SRC_PINNED_HOST || n == 0)
+    return enqueue_resident(p->kind, p->dtype, p->op, p->prec, t, cu, col, n, out, p->part, stream);
 
   // Pinned host: copy chunks of whole segments into the staging ring on the
   // copy stream while the scan of earlier chunks runs on `stream`.
@@ -558,6 +622,28 @@ int agg_run(agg_plan_t p, const void* col, int64_t n, agg_result* out, void* str
     p->slot_used[slot] = true;
   }
   return launch(combine_fn, 1, kCombineThreads, &c, stream);
+}
+
+int agg_run_noalloc(int32_t dtype, int32_t op, int32_t prec, int32_t src, const void* col, int64_t n,
+                    agg_result* out, void* stream_v) {
+  const int kind = kind_of(dtype, op, prec);
+  if (kind < 0 || !out || n < 0 || n > kMaxItems || (n > 0 && !col)) return AGG_E_INVALID;
+  if (src != AGG_SRC_DEVICE && src != AGG_SRC_ZEROCOPY) return AGG_E_INVALID;  // no staging ring
+  const int w = width_of(dtype);
+  if (n > 0 && reinterpret_cast<uintptr_t>(col) % (uintptr_t)w != 0) return AGG_E_INVALID;
+  int dev = 0;
+  RET_IF(current_device(&dev));
+  agg_shape s;
+  shape_of(dtype, n, &s);
+  if (s.nseg > kScratchSlots) return AGG_E_INVALID;  // cannot happen: a canonical shape has <= 8192 segments
+  if (n > 0) RET_IF(check_pointer(col, n * w, src == AGG_SRC_ZEROCOPY ? AGG_SRC_PINNED_HOST : AGG_SRC_DEVICE, dev));
+  RET_IF(check_out_pointer(out, sizeof(agg_result), dev));
+  uint64_t* part = nullptr;
+  RET_IF(scratch_of(dev, &part));
+  agg_tune t;
+  tune_for(kind, src, n * w, &t);
+  return enqueue_resident(kind, dtype, op, prec, t, g_dev[dev].cu, col, n, out, part,
+                          static_cast<hipStream_t>(stream_v));
 }
 
 namespace {
