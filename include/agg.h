@@ -59,14 +59,14 @@ enum { AGG_I32 = 0, AGG_I64 = 1, AGG_F32 = 2 };
 enum { AGG_SUM = 0, AGG_MIN = 1, AGG_MAX = 2, AGG_COUNT = 3, AGG_AVG = 4 };
 /* Float SUM / AVG precision modes (ignored for other dtype/op pairs):
  *   NEUMAIER     per-lane Neumaier-compensated float32 (sum, correction)
- *                pairs, renormalised by an exact two-sum after every 4 rounds
+ *                pairs, renormalised by an exact two-sum after every 8 rounds
  *                of loads and after the last, combined across lanes by exact
  *                two-sum (then renormalised); each segment partial is
  *                sum + correction in double; double combine.  A-priori bound:
- *                |error| <= 1.01 ((14 ceil(m/4) + 24) u^2 + (k + 8) v) sum|x|
+ *                |error| <= 1.01 ((44 ceil(m/8) + 24) u^2 + (k + 8) v) sum|x|
  *                with u = 2^-24, v = 2^-53, m = seg_bytes / 1024 items per
  *                lane accumulator and k = ceil(nseg / 256); for 2^30 items
- *                that is 6.5e-12 sum|x|.
+ *                that is 1.0e-11 sum|x|.
  *   F32          plain float32 everywhere, including the final combine.
  *   F64_COMBINE  plain float32 lanes and wave reduction, segment partials
  *                widened to double, double combine. */
@@ -214,8 +214,9 @@ int agg_batch_destroy(agg_batch_t batch);
 /* Work items, total segments and the launch parameters the batch graph uses. */
 int agg_batch_info(agg_batch_t batch, int64_t* nitems, int64_t* nseg_total, agg_tune* tune);
 
-/* Re-capture the batch graph with other launch parameters (results unchanged).
- * Waits for the batch's previous runs to finish. */
+/* Re-capture the batch graph with other launch parameters (results unchanged;
+ * waves_per_block at most 8 for batches).  Waits for the batch's previous runs
+ * to finish. */
 int agg_batch_retune(agg_batch_t batch, const agg_tune* tune);
 
 /* Time the batch graph under a fixed set of launch parameters on `stream`

@@ -266,7 +266,7 @@ def float_sum_bound_coeff(prec, n: int) -> float:
     mode `prec`, as a multiple of sum |x| (include/agg.h): with u = 2^-24,
     v = 2^-53, m = seg_bytes / 1024 and k = ceil(nseg / 256) of the canonical
     shape, gamma_d(w) = d w / (1 - d w):
-    compensated 1.01 ((14 ceil(m/4) + 24) u^2 + (k + 8) v); plain
+    compensated 1.01 ((44 ceil(m/8) + 24) u^2 + (k + 8) v); plain
     gamma_{m+k+18}(u); f64-combine gamma_{m+8}(u) + gamma_{k+8}(v) (1 + gamma_{m+8}(u))."""
     p = _code(prec, PRECS, "prec")
     s = canonical_shape(F32, n)
@@ -281,7 +281,7 @@ def float_sum_bound_coeff(prec, n: int) -> float:
     if p == PREC_F64_COMBINE:
         g = gamma(m + 8, u)
         return g + gamma(k + 8, v) * (1.0 + g)
-    return 1.01 * ((14 * -(-m // 4) + 24) * u * u + (k + 8) * v)
+    return 1.01 * ((44 * -(-m // 8) + 24) * u * u + (k + 8) * v)
 
 
 def default_tune(dtype, op, n: int, prec="neumaier", src="device") -> Tune:

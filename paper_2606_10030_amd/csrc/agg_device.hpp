@@ -170,9 +170,10 @@ template <> struct Fold<K_SUM_F32_F64C> : FoldSumF32<true> {};
 // renormalised by an exact two-sum, (s, c) <- (fl(s + c), error): the value
 // s + c is unchanged and |c| drops back to at most u |s|.  The correction then
 // only ever sums a few errors, and the rounding it adds is linear in m:
-// at most ceil(m / R) * R (R + 3) / 2 * u^2 * sum|x| for R rounds per block.
+// at most ceil(m / R) * R (R + 3) / 2 * u^2 * sum|x| for R rounds per block
+// (R = 8: 44 ceil(m / 8) u^2 sum|x|).
 struct NeuPair { float s, c; };
-constexpr int kNeuRenormRounds = 4;
+constexpr int kNeuRenormRounds = 8;
 template <> struct Fold<K_SUM_F32_NEU> {
   static constexpr int W = 4, V = 4;
   using acc = NeuPair; using part = double;
@@ -235,15 +236,18 @@ __device__ __forceinline__ void round_done(typename Fold<K>::acc* a, int64_t r) 
   }
 }
 
-// The same inside an unrolled group of U rounds whose first round index is a
-// multiple of U (U a multiple of the block length): position u decides it at
-// compile time.
+// The same inside an unrolled group of U rounds starting at round r0, a
+// multiple of U: when U is a multiple of the block length, position u alone
+// decides it (at compile time); otherwise the round index does.
 template <int K, int U, int u>
-__device__ __forceinline__ void round_done_unrolled(typename Fold<K>::acc* a) {
+__device__ __forceinline__ void round_done_unrolled(typename Fold<K>::acc* a, int64_t r0) {
   constexpr int R = renorm_rounds<K>();
   if constexpr (R > 0) {
-    static_assert(U % R == 0, "the unroll must hold whole renormalisation blocks");
-    if constexpr ((u + 1) % R == 0) renorm_all<K>(a);
+    if constexpr (U % R == 0) {
+      if constexpr ((u + 1) % R == 0) renorm_all<K>(a);
+    } else {
+      round_done<K>(a, r0 + u);
+    }
   }
 }
 
@@ -338,9 +342,9 @@ __device__ __forceinline__ T wave_reduce(T x, M merge) {
 // Fold U loaded rounds in order (fold_round(u) folds round u of the group),
 // renormalising where a block closes.
 template <int K, int U, class FR, int... us>
-__device__ __forceinline__ void fold_unrolled(typename Fold<K>::acc* a, FR&& fold_round,
+__device__ __forceinline__ void fold_unrolled(typename Fold<K>::acc* a, int64_t r0, FR&& fold_round,
                                               std::integer_sequence<int, us...>) {
-  ((fold_round(us), round_done_unrolled<K, U, us>(a)), ...);
+  ((fold_round(us), round_done_unrolled<K, U, us>(a, r0)), ...);
 }
 
 
@@ -372,7 +376,7 @@ __device__ __forceinline__ typename Fold<K>::acc fold_segment(const char* __rest
     u32x4 x[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) x[u] = load_vec<NT, AL, F::W>(p + (r + u) * kRoundBytes);
-    fold_unrolled<K, U>(a, [&](int u) { F::add_vec(a, x[u]); }, std::make_integer_sequence<int, U>());
+    fold_unrolled<K, U>(a, r, [&](int u) { F::add_vec(a, x[u]); }, std::make_integer_sequence<int, U>());
   }
   for (; r < full; ++r) {
     F::add_vec(a, load_vec<NT, AL, F::W>(p + r * kRoundBytes));

@@ -113,7 +113,7 @@ __device__ __forceinline__ typename Fold<K>::acc fold_segment_filtered(const cha
       load_filter<FB, FW, NT, AL>(f + (r + u) * RFB, fw[u]);
     }
     fold_unrolled<K, U>(
-        a, [&](int u) { fold_round(kCount ? u32x4{0, 0, 0, 0} : x[u], fw[u]); },
+        a, r, [&](int u) { fold_round(kCount ? u32x4{0, 0, 0, 0} : x[u], fw[u]); },
         std::make_integer_sequence<int, U>());
   }
   for (; r < full; ++r) {

@@ -10,7 +10,7 @@ round-to-nearest, no fused operations), the order of operations that
   r = 0, 1, ..., each of the 4 components into its own accumulator; a
   partial last round gives a lane its whole vector or its first items;
 * compensated mode: Neumaier's update per item, an exact two-sum
-  renormalisation of every accumulator after each block of 4 rounds and once
+  renormalisation of every accumulator after each block of 8 rounds and once
   after the last round, components merged as (c0 + c1) + (c2 + c3), the 64
   lanes merged as a balanced tree in lane order (the butterfly's merges are
   symmetric, so lane 0's value is that tree), segment partial s + c in double;
@@ -29,7 +29,7 @@ import numpy as np
 
 F32 = np.float32
 F64 = np.float64
-RENORM_ROUNDS = 4
+RENORM_ROUNDS = 8
 ROUND_ITEMS = 256          # 64 lanes x 4 float32 items per 1 KiB round
 
 

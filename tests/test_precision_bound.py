@@ -1,8 +1,8 @@
 """The float32 SUM error bounds of `aggcheck.py`, exercised on the CPU.
 
 * The compensated lane fold (Neumaier's update, exact two-sum renormalisation
-  every 4 rounds), modelled step by step in numpy float32, stays within the
-  linear per-lane bound ceil(m/4) * 14 * u^2 * sum|x| on inputs built to make
+  every 8 rounds), modelled step by step in numpy float32, stays within the
+  linear per-lane bound ceil(m/8) * 44 * u^2 * sum|x| on inputs built to make
   the correction's own roundings add up; without the renormalisation the same
   inputs exceed that bound (the quadratic term of the cascaded-summation bound
   of Ogita, Rump and Oishi 2005, Prop. 4.5, is real).
