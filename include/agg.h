@@ -214,9 +214,8 @@ int agg_batch_destroy(agg_batch_t batch);
 /* Work items, total segments and the launch parameters the batch graph uses. */
 int agg_batch_info(agg_batch_t batch, int64_t* nitems, int64_t* nseg_total, agg_tune* tune);
 
-/* Re-capture the batch graph with other launch parameters (results unchanged;
- * waves_per_block at most 8 for batches).  Waits for the batch's previous runs
- * to finish. */
+/* Re-capture the batch graph with other launch parameters (results
+ * unchanged).  Waits for the batch's previous runs to finish. */
 int agg_batch_retune(agg_batch_t batch, const agg_tune* tune);
 
 /* Time the batch graph under a fixed set of launch parameters on `stream`

@@ -157,9 +157,27 @@ __device__ __forceinline__ uint64_t mix64(uint64_t k) {  // MurmurHash3's 64-bit
 
 __device__ __forceinline__ int64_t ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// The hash of a key that places it in LDS tables and partitions.  int64
+// keys: the 64-bit finaliser above.  int32 keys: one 32 x 64-bit multiply by
+// an odd constant (2^64 / golden ratio) and a fold of the high half into the
+// low one -- two quarter-rate multiplies instead of the finaliser's eight,
+// and a bijection on the 32-bit keys; the top bits (partitions, passes) come
+// from the product's high half, the low bits (slots) mix both halves, and
+// bits 32.. give the probe step.
+template <int KD>
+__device__ __forceinline__ uint64_t key_hash(int64_t k) {
+  if constexpr (KD == AGG_I32) {
+    const uint64_t p = (uint64_t)(uint32_t)k * 0x9E3779B97F4A7C15ull;
+    return p ^ (p >> 32);
+  } else {
+    return mix64((uint64_t)k);
+  }
+}
+
 // Partition of a key: the top bits of its hash (table slots use the low bits).
+template <int KD>
 __device__ __forceinline__ uint32_t part_of(int64_t k, int bits) {
-  return (uint32_t)(mix64((uint64_t)k) >> (64 - bits));
+  return (uint32_t)(key_hash<KD>(k) >> (64 - bits));
 }
 
 // Order-preserving map of non-NaN floats to int32 (and back).
@@ -309,7 +327,7 @@ __global__ void __launch_bounds__(kThreads) gb_hist_kernel(Args a) {
     for (int r = 0; r < kAggRows; ++r) kk[r] = load_key<KD>(a.keys, std::min<int64_t>(base + (int64_t)r * kThreads, hi - 1));
 #pragma unroll
     for (int r = 0; r < kAggRows; ++r)
-      if (base + (int64_t)r * kThreads < hi) atomicAdd(&h[part_of(kk[r], a.pt.bits)], 1u);
+      if (base + (int64_t)r * kThreads < hi) atomicAdd(&h[part_of<KD>(kk[r], a.pt.bits)], 1u);
   }
   __syncthreads();
   for (int e = threadIdx.x; e < P; e += kThreads) a.pt.hist[(int64_t)e * a.pt.g1 + blockIdx.x] = h[e];
@@ -413,7 +431,7 @@ __global__ void __launch_bounds__(kTileThreads) gb_scatter_tiled_kernel(Args a) 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (r * kTileThreads + tid < rows) {
-        pp[r] = part_of((int64_t)k[r], a.pt.bits);
+        pp[r] = part_of<KD>((int64_t)k[r], a.pt.bits);
         rank[r] = atomicAdd(&tcnt[pp[r]], 1u);
       }
     }
@@ -450,7 +468,7 @@ __global__ void __launch_bounds__(kTileThreads) gb_scatter_tiled_kernel(Args a) 
     __syncthreads();
     for (int j = tid; j < rows; j += kTileThreads) {
       uint32_t q;
-      if constexpr (HASV) q = part_of((int64_t)skey[j], a.pt.bits);
+      if constexpr (HASV) q = part_of<KD>((int64_t)skey[j], a.pt.bits);
       else q = spart[j];
       const uint32_t pos = cur[q] + (uint32_t)j - toff[q];
       if ((int64_t)pos >= a.n) continue;  // cannot happen: counts match the histogram
@@ -495,7 +513,7 @@ struct LdsTable {
   int64_t dig[kDig ? (L + 1) * kLdsDigits : 1];  // digits 1..7 of a float sum
   int32_t flags[kDig ? L + 1 : 1];
 
-  __device__ void clear() {
+  __device__ __forceinline__ void clear() {
     for (int e = threadIdx.x; e <= L; e += NT) {
       if (e < L) key[e] = kMark;
       cnt[e] = 0;
@@ -507,11 +525,30 @@ struct LdsTable {
     }
   }
 
+  // The slot holding key k (hash hk), claiming an empty one; -1 if none
+  // within kLdsProbes probes.  Double hashing: an odd step from the hash's
+  // high half, so probe chains do not cluster (a wave waits for its longest
+  // chain).
+  __device__ __forceinline__ int slot_of(KT k, uint64_t hk) {
+    if (k == kMark) return L;
+    int h = (int)(hk & (L - 1));
+    const int step = (int)(((hk >> 32) | 1) & (L - 1));
+    for (int p = 0; p < kLdsProbes; ++p, h = (h + step) & (L - 1)) {
+      const KT cur = key[h];
+      if (cur == k) return h;
+      if (cur == kMark) {
+        const KT prev = (KT)atomicCAS(reinterpret_cast<UKT*>(&key[h]), (UKT)kMark, (UKT)k);
+        if (prev == kMark || prev == k) return h;
+      }
+    }
+    return -1;
+  }
+
   // Rows first, first + step, ... below last whose key hash has the bits
   // (hash >> sub_shift) & sub_mask equal to sub; a row whose key finds no
   // slot within kLdsProbes goes to the global table.
   template <int VD, bool ROWS = false>  // ROWS: keys holds staged (key, value) records
-  __device__ void fold_rows(const Table& t, const void* keys, const void* vals, int64_t first, int64_t last,
+  __device__ __forceinline__ void fold_rows(const Table& t, const void* keys, const void* vals, int64_t first, int64_t last,
                             int64_t step, uint32_t sub_shift, uint32_t sub_mask, uint32_t sub) {
     constexpr int R = kAggRows;
     for (int64_t base = first; base < last; base += step * R) {
@@ -540,33 +577,26 @@ struct LdsTable {
           }
         }
       }
+      // every row's loads are complete before the first row is folded: left
+      // alone, the compiler sinks a value load into the branch that uses it,
+      // and that load's whole latency then stalls the wave
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        __asm__ volatile("" : "+v"(kk[r]));
+        if constexpr (G != G_COUNT) {
+          if constexpr (VD == AGG_F32) __asm__ volatile("" : "+v"(fvv[r]));
+          else __asm__ volatile("" : "+v"(ivv[r]));
+        }
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (base + r * step >= last) break;
         const KT k = (KT)kk[r];
-        const uint64_t hk = mix64((uint64_t)kk[r]);
+        const uint64_t hk = key_hash<KD>(kk[r]);
         if (((uint32_t)(hk >> sub_shift) & sub_mask) != sub) continue;  // another pass's row
         bool in_lds = true;
         if constexpr (kDig) in_lds = lds_digits_hold(fvv[r]);
-        int s = -1;
-        if (!in_lds) {
-          // outside the LDS slot's digits: the global table below
-        } else if (k == kMark) {
-          s = L;
-        } else {
-          // double hashing: an odd step from the hash's high half, so probe
-          // chains do not cluster (a wave waits for its longest chain)
-          int h = (int)(hk & (L - 1));
-          const int step = (int)(((hk >> 32) | 1) & (L - 1));
-          for (int p = 0; p < kLdsProbes; ++p, h = (h + step) & (L - 1)) {
-            const KT cur = key[h];
-            if (cur == k) { s = h; break; }
-            if (cur == kMark) {
-              const KT prev = (KT)atomicCAS(reinterpret_cast<UKT*>(&key[h]), (UKT)kMark, (UKT)k);
-              if (prev == kMark || prev == k) { s = h; break; }
-            }
-          }
-        }
+        const int s = in_lds ? slot_of(k, hk) : -1;  // outside the LDS slot's digits: the global table
         if (s >= 0) {
           if constexpr (kDig) {
             at_add<true>(&cnt[s], 1u);
@@ -592,7 +622,7 @@ struct LdsTable {
     }
   }
 
-  __device__ void flush(const Table& t) {
+  __device__ __forceinline__ void flush(const Table& t) {
     for (int e = threadIdx.x; e <= L; e += NT) {
       const KT k = e < L ? key[e] : kMark;
       if (e < L ? k == kMark : cnt[L] == 0) continue;

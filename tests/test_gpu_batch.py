@@ -103,7 +103,7 @@ def test_launch_parameters_do_not_change_batch_bits(agg):
         for i, (g, s) in enumerate(zip(got, ref)):
             assert same_bits(g, s), f"tune u{u} w{w} b{bp}: column {i} differs"
     t, ms = b.autotune()
-    assert ms > 0 and t.unroll in (8, 16, 32)
+    assert ms > 0 and t.unroll in (4, 8, 16)  # the batch autotuner's candidates (32 spills registers)
     got = b.run()
     for g, s in zip(got, ref):
         assert same_bits(g, s)

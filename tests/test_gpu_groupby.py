@@ -354,3 +354,30 @@ def test_groupby_float_sum_rounding_cases(agg):
     got = g.run(torch.from_numpy(keys).to("cuda"), torch.from_numpy(vals).to("cuda"))
     assert [x[2] for x in got] == [want[k] for k in sorted(want)]
     compare(got, oracle.groupby(keys, vals, "sum"), "rounding cases")
+
+
+def test_groupby_declared_max_groups_does_not_change_groups(agg):
+    """The declared max_groups picks the path (direct, direct in two passes,
+    partitioned); over the same 12 groups every choice gives the same groups
+    bit for bit, and the oracle's, including the marker key and float values
+    outside the LDS digits."""
+    import torch
+    n = 300_007
+    for kdt in ("i32", "i64"):
+        keys = make_keys(n, kdt, 12, seed=92)   # the pool holds the marker key (INT_MIN)
+        dk = torch.from_numpy(keys).to("cuda")
+        for vdt, op in (("f32", "sum"), ("i64", "sum"), ("i32", "min"), ("f32", "max"), ("i32", "count")):
+            vals = make_vals(n, vdt, seed=93)
+            if vdt == "f32":
+                vals[::777] = np.float32(2.0 ** 100)
+                vals[::555] = np.float32(2.0 ** -120)
+            dv = torch.from_numpy(vals).to("cuda")
+            want = oracle.groupby(keys, vals, op)
+            assert len(want) == 12
+            first = None
+            for mg in (12, 16, 17, 5000, 100_000, 6_000_000):
+                got = agg.GroupBy(kdt, vdt, op, max_n=n, max_groups=mg).run(dk, dv)
+                compare(got, want, f"{kdt} {vdt} {op} max_groups={mg}")
+                if first is None:
+                    first = got
+                assert got == first, f"{kdt} {vdt} {op}: max_groups={mg} differs from max_groups=12"
