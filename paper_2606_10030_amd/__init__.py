@@ -239,12 +239,18 @@ def _torch():
     return torch
 
 
+_TENSOR_DTYPES = None
+
+
 def _dtype_of_tensor(t) -> int:
-    torch = _torch()
-    m = {torch.int32: I32, torch.int64: I64, torch.float32: F32}
-    if t.dtype not in m:
+    global _TENSOR_DTYPES
+    if _TENSOR_DTYPES is None:
+        torch = _torch()
+        _TENSOR_DTYPES = {torch.int32: I32, torch.int64: I64, torch.float32: F32}
+    code = _TENSOR_DTYPES.get(t.dtype)
+    if code is None:
         raise TypeError(f"unsupported column dtype {t.dtype}")
-    return m[t.dtype]
+    return code
 
 
 def _stream_handle(stream) -> int:
@@ -370,6 +376,7 @@ class Plan:
                               ctypes.byref(tune) if tune is not None else None), "agg_plan")
         self._h = h
         self._host_out = None
+        self._agg_run = lib().agg_run  # looked up once: enqueue is on the small-call path
 
     def info(self, n: int):
         s, t = Shape(), Tune()
@@ -392,7 +399,9 @@ class Plan:
         """Enqueue agg_run writing the 32-byte result to `out` (tensor or address); no sync."""
         ptr, nn = self._col_args(col, n)
         optr = out if isinstance(out, int) else out.data_ptr()
-        _check(lib().agg_run(self._h, ptr, nn, optr, _stream_handle(stream)), "agg_run")
+        rc = self._agg_run(self._h, ptr, nn, optr, _stream_handle(stream))
+        if rc != OK:
+            _check(rc, "agg_run")
 
     def run(self, col, n: Optional[int] = None, stream=None) -> dict:
         """Run and wait; returns the decoded result."""

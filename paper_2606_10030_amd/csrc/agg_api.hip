@@ -205,14 +205,9 @@ void tune_for(int kind, int32_t src, int64_t bytes, agg_tune* t) {
 // the plain kinds (agg_batch_autotune refines it).
 void batch_builtin_tune(agg_tune* t) { builtin_tune_for(K_SUM_I32, t); }
 
-// The memory behind [p, p + bytes) must be of the kind `src` names.
-int check_pointer(const void* p, int64_t bytes, int32_t src, int dev) {
-  hipPointerAttribute_t at;
-  std::memset(&at, 0, sizeof at);
-  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return AGG_E_INVALID;
-  }
+namespace {
+// The checks of check_pointer on attributes already queried.
+int check_pointer_with(const hipPointerAttribute_t& at, const void* p, int64_t bytes, int32_t src, int dev) {
   if (src == AGG_SRC_DEVICE) {
     if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged) return AGG_E_INVALID;
     if (at.type == hipMemoryTypeDevice && at.device != dev) return AGG_E_INVALID;
@@ -232,9 +227,23 @@ int check_pointer(const void* p, int64_t bytes, int32_t src, int dev) {
   }
   return AGG_OK;
 }
+}  // namespace
+
+// The memory behind [p, p + bytes) must be of the kind `src` names.
+int check_pointer(const void* p, int64_t bytes, int32_t src, int dev) {
+  hipPointerAttribute_t at;
+  std::memset(&at, 0, sizeof at);
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return AGG_E_INVALID;
+  }
+  return check_pointer_with(at, p, bytes, src, dev);
+}
 
 // A result buffer: device memory of `dev` or page-locked host memory, with
-// room for `bytes` bytes.
+// room for `bytes` bytes.  (Each call is two runtime queries, about 0.05 us
+// each on MI355X; they are not cached across calls, since a range freed and
+// reused would then pass unchecked.)
 int check_out_pointer(const void* p, int64_t bytes, int dev) {
   hipPointerAttribute_t at;
   std::memset(&at, 0, sizeof at);
@@ -243,8 +252,8 @@ int check_out_pointer(const void* p, int64_t bytes, int dev) {
     return AGG_E_INVALID;
   }
   if (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged)
-    return check_pointer(p, bytes, AGG_SRC_DEVICE, dev);
-  if (at.type == hipMemoryTypeHost) return check_pointer(p, bytes, AGG_SRC_PINNED_HOST, dev);
+    return check_pointer_with(at, p, bytes, AGG_SRC_DEVICE, dev);
+  if (at.type == hipMemoryTypeHost) return check_pointer_with(at, p, bytes, AGG_SRC_PINNED_HOST, dev);
   return AGG_E_INVALID;
 }
 

@@ -372,11 +372,33 @@ __device__ __forceinline__ typename Fold<K>::acc fold_segment(const char* __rest
   for (int v = 0; v < F::V; ++v) a[v] = F::identity();
   const char* p = seg + lane * kVecBytes;
   int64_t r = 0;
-  for (; r + U <= full; r += U) {
-    u32x4 x[U];
+  if constexpr (K == K_SUM_F32_NEU && U <= 8) {
+    // The compensated fold costs several operations an item: the next U
+    // rounds' loads are issued before the current U are folded, so a wave's
+    // arithmetic overlaps its own memory wait (same rounds, same order).
+    // Two groups of loads in flight take 8 registers a round: up to U = 8.
+    if (U <= full) {
+      u32x4 x[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) x[u] = load_vec<NT, AL, F::W>(p + (r + u) * kRoundBytes);
-    fold_unrolled<K, U>(a, r, [&](int u) { F::add_vec(a, x[u]); }, std::make_integer_sequence<int, U>());
+      for (int u = 0; u < U; ++u) x[u] = load_vec<NT, AL, F::W>(p + u * kRoundBytes);
+      for (; r + 2 * U <= full; r += U) {
+        u32x4 y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) y[u] = load_vec<NT, AL, F::W>(p + (r + U + u) * kRoundBytes);
+        fold_unrolled<K, U>(a, r, [&](int u) { F::add_vec(a, x[u]); }, std::make_integer_sequence<int, U>());
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = y[u];
+      }
+      fold_unrolled<K, U>(a, r, [&](int u) { F::add_vec(a, x[u]); }, std::make_integer_sequence<int, U>());
+      r += U;
+    }
+  } else {
+    for (; r + U <= full; r += U) {
+      u32x4 x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = load_vec<NT, AL, F::W>(p + (r + u) * kRoundBytes);
+      fold_unrolled<K, U>(a, r, [&](int u) { F::add_vec(a, x[u]); }, std::make_integer_sequence<int, U>());
+    }
   }
   for (; r < full; ++r) {
     F::add_vec(a, load_vec<NT, AL, F::W>(p + r * kRoundBytes));

@@ -109,14 +109,21 @@ def _serve_checked(agg, nreq, n_max, arena_items, hot_items, big_shipped, seed, 
     import oracle
     import torch
     t0 = time.time()
+
+    def progress(what):  # large configurations take minutes to set up: say what is done
+        print(f"serve check: {what} at {time.time() - t0:.1f}s", flush=True)
+
     arena = torch.empty(arena_items, dtype=torch.int32, pin_memory=True)
     datagen.fill_ptr(arena.data_ptr(), arena_items, "i32", "uniform", seed)
+    progress(f"arena of {arena_items} items generated")
     hot_h = torch.empty(hot_items, dtype=torch.int32, pin_memory=True)
     datagen.fill_ptr(hot_h.data_ptr(), hot_items, "i32", "uniform", seed + 1)
     hot = hot_h.to("cuda")
+    progress(f"hot column of {hot_items} items generated and copied")
     ro_arena = oracle.RangeOracle(arena.data_ptr(), arena_items, oracle.I32)
+    progress("oracle tables over the arena built")
     ro_hot = oracle.RangeOracle(hot_h.data_ptr(), hot_items, oracle.I32)
-    print(f"serve check: inputs and oracle tables in {time.time() - t0:.1f}s", flush=True)
+    progress("oracle tables over the hot column built")
     cap = 55e9 / (0.7 * mean_bytes(10_000, n_max, 4))
     specs = request_stream(nreq, seed=seed, n_min=10_000, n_max=n_max, rate_per_s=0.8 * cap, resident_frac=0.3,
                            hot_items=hot_items, arena_items=arena_items)
@@ -144,6 +151,8 @@ def _serve_checked(agg, nreq, n_max, arena_items, hot_items, big_shipped, seed, 
     assert sm["peak_reserved_bytes"] <= budget
     checked = 0
     for i, (s, got, st) in enumerate(zip(specs, results, stats)):
+        if i and i % 2000 == 0:
+            progress(f"{i} results checked")
         assert st["status"] == 0, f"request {i}: status {st['status']}"
         want = (ro_hot if s["resident"] else ro_arena).aggregate(s["offset"], s["n"], s["op"])
         ctx = f"request {i} ({s['op']}, n={s['n']}, offset={s['offset']}, resident={s['resident']})"
@@ -184,6 +193,8 @@ def test_serving_at_scale_checked_against_oracle(agg):
                            "of PCIe time) runs only with AGG_SERVE_FULL=1")
 def test_serving_full_configuration_checked_against_oracle(agg):
     """The full serving configuration: 10^4 requests, lengths log-uniform in
-    [1e4, 2^33] int32 (up to 32 GiB), every result checked."""
+    [1e4, 2^33] int32 (up to 32 GiB), every result checked.  Run it with
+    pytest -s: setup and serving take minutes, and the progress lines (the
+    test's and the server's) should reach the console as they happen."""
     _serve_checked(agg, nreq=10_000, n_max=1 << 33, arena_items=1 << 33, hot_items=1 << 33, big_shipped=0, seed=13,
                    out_name="serve_full_check.json")
