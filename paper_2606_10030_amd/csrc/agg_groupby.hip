@@ -498,24 +498,30 @@ __global__ void __launch_bounds__(kTileThreads) gb_scatter_tiled_kernel(Args a) 
 
 // One workgroup's table: L hashed slots keyed in the key column's own width
 // (4-byte keys fit twice the slots of 8-byte ones), plus slot L for the one
-// key whose bit pattern marks an empty slot.
-template <int G, int KD, int L_, int NT>
+// key whose bit pattern marks an empty slot.  Each slot has REP copies of its
+// accumulators; lane l of a wave updates copy l % REP, so the lanes of one
+// wave instruction whose rows share a key spread over REP addresses (LDS
+// atomics on one address serialise), and the flush merges the copies (exact
+// integer merges: the results do not depend on REP).
+template <int G, int KD, int L_, int NT, int REP = 1>
 struct LdsTable {
   using KT = typename std::conditional<KD == AGG_I32, int32_t, int64_t>::type;
   using UKT = typename std::conditional<KD == AGG_I32, unsigned int, unsigned long long>::type;
   static constexpr KT kMark = std::numeric_limits<KT>::min();  // empty hashed slot
   static constexpr int L = L_;
+  static constexpr int E = (L + 1) * REP;  // accumulator entries: slot s, copy c at s * REP + c
   static constexpr bool kDig = G == G_SUM_F32;
   static constexpr bool kVal = !kDig && G != G_COUNT;
+  static_assert((REP & (REP - 1)) == 0 && REP <= 64, "copies: a power of two, at most a wave");
   KT key[L];
-  uint32_t cnt[L + 1];  // rows per table stay below 2^32 (a workgroup's share is at most 2^28 rows)
-  int64_t val[kVal ? L + 1 : 1];
-  int64_t dig[kDig ? (L + 1) * kLdsDigits : 1];  // digits 1..7 of a float sum
-  int32_t flags[kDig ? L + 1 : 1];
+  uint32_t cnt[E];  // rows per table stay below 2^32 (a workgroup's share is at most 2^28 rows)
+  int64_t val[kVal ? E : 1];
+  int64_t dig[kDig ? E * kLdsDigits : 1];  // digits 1..7 of a float sum
+  int32_t flags[kDig ? E : 1];
 
   __device__ __forceinline__ void clear() {
-    for (int e = threadIdx.x; e <= L; e += NT) {
-      if (e < L) key[e] = kMark;
+    for (int e = threadIdx.x; e < L; e += NT) key[e] = kMark;
+    for (int e = threadIdx.x; e < E; e += NT) {
       cnt[e] = 0;
       if constexpr (kVal) val[e] = val_identity<G>();
       if constexpr (kDig) {
@@ -596,8 +602,9 @@ struct LdsTable {
         if (((uint32_t)(hk >> sub_shift) & sub_mask) != sub) continue;  // another pass's row
         bool in_lds = true;
         if constexpr (kDig) in_lds = lds_digits_hold(fvv[r]);
-        const int s = in_lds ? slot_of(k, hk) : -1;  // outside the LDS slot's digits: the global table
-        if (s >= 0) {
+        const int slot = in_lds ? slot_of(k, hk) : -1;  // outside the LDS slot's digits: the global table
+        if (slot >= 0) {
+          const int s = slot * REP + (int)(threadIdx.x & (REP - 1));  // this lane's copy
           if constexpr (kDig) {
             at_add<true>(&cnt[s], 1u);
             if (!__builtin_isfinite(fvv[r])) {
@@ -625,17 +632,31 @@ struct LdsTable {
   __device__ __forceinline__ void flush(const Table& t) {
     for (int e = threadIdx.x; e <= L; e += NT) {
       const KT k = e < L ? key[e] : kMark;
-      if (e < L ? k == kMark : cnt[L] == 0) continue;
+      uint64_t c = 0;
+      for (int r = 0; r < REP; ++r) c += cnt[e * REP + r];
+      if (e < L ? k == kMark : c == 0) continue;
       const int64_t g = global_slot(t, (int64_t)k);
       if (g < 0) continue;
-      atomicAdd(reinterpret_cast<unsigned long long*>(t.cnt + g), (unsigned long long)cnt[e]);
-      if constexpr (G == G_SUM_INT) atomicAdd(reinterpret_cast<unsigned long long*>(t.val + g), (unsigned long long)val[e]);
-      if constexpr (G == G_MIN_INT || G == G_MIN_F32) atomicMin(reinterpret_cast<long long*>(t.val + g), (long long)val[e]);
-      if constexpr (G == G_MAX_INT || G == G_MAX_F32) atomicMax(reinterpret_cast<long long*>(t.val + g), (long long)val[e]);
+      atomicAdd(reinterpret_cast<unsigned long long*>(t.cnt + g), (unsigned long long)c);
+      if constexpr (kVal) {
+        int64_t v = val[e * REP];
+        for (int r = 1; r < REP; ++r) {
+          const int64_t w = val[e * REP + r];
+          if constexpr (G == G_SUM_INT) v = (int64_t)((uint64_t)v + (uint64_t)w);
+          else if constexpr (G == G_MIN_INT || G == G_MIN_F32) v = w < v ? w : v;
+          else v = w > v ? w : v;
+        }
+        if constexpr (G == G_SUM_INT) atomicAdd(reinterpret_cast<unsigned long long*>(t.val + g), (unsigned long long)v);
+        if constexpr (G == G_MIN_INT || G == G_MIN_F32) atomicMin(reinterpret_cast<long long*>(t.val + g), (long long)v);
+        if constexpr (G == G_MAX_INT || G == G_MAX_F32) atomicMax(reinterpret_cast<long long*>(t.val + g), (long long)v);
+      }
       if constexpr (kDig) {
-        if (flags[e]) atomicOr(t.flags + g, flags[e]);
+        int32_t f = 0;
+        for (int r = 0; r < REP; ++r) f |= flags[e * REP + r];
+        if (f) atomicOr(t.flags + g, f);
         for (int d = 0; d < kLdsDigits; ++d) {
-          const int64_t v = dig[e * kLdsDigits + d];
+          uint64_t v = 0;  // digits add mod 2^64, as in the global table
+          for (int r = 0; r < REP; ++r) v += (uint64_t)dig[(e * REP + r) * kLdsDigits + d];
           if (v) atomicAdd(reinterpret_cast<unsigned long long*>(t.dig + g * kDigits + d + 1), (unsigned long long)v);
         }
       }
@@ -643,12 +664,28 @@ struct LdsTable {
   }
 };
 
+// Float sums of few groups (at most kFewGroups): with a full-size table a
+// wave's 64 rows fall on about as many slots as there are groups, and the
+// LDS atomics of lanes that meet on a slot serialise (measured on MI355X: a
+// 64-bit add from a wave whose rows spread over 16 slots takes about 24
+// clocks, over 64 addresses 6); a float row makes three (two digits and the
+// count).  A 256-slot table whose slots carry kFewCopies copies of the
+// accumulators (lane l updates copy l % kFewCopies) cuts the meetings by that
+// factor: 16 groups, 2^28 rows, 0.626 -> 0.594 ms.  For COUNT and integer
+// values (one or two atomics a row) the smaller table's longer probe chains
+// cost more than the copies save (0.338 -> 0.348 ms, 0.526 -> 0.561 ms), so
+// they keep the full table.
+constexpr int kFewGroups = 32;
+constexpr int kFewCopies = 4;
+constexpr int kFewSlots = 256;
+
 // Direct path: every workgroup sweeps the rows grid-stride into one LDS
 // table, in 2^sub_bits passes (each taking the keys of one sub-partition:
 // the top bits of the key's hash) when the groups need more than one table.
-template <int KD, int VD, int G>
+template <int KD, int VD, int G, bool FEW>
 __global__ void __launch_bounds__(kDirectThreads) gb_aggregate_kernel(Args a) {
-  __shared__ LdsTable<G, KD, lds_slots<G, KD>(), kDirectThreads> tab;
+  static_assert(!FEW || G == G_SUM_F32, "the few-groups table is for float sums");
+  __shared__ LdsTable<G, KD, FEW ? kFewSlots : lds_slots<G, KD>(), kDirectThreads, FEW ? kFewCopies : 1> tab;
   const uint32_t sub_mask = (1u << a.pt.sub_bits) - 1u;
   const uint32_t sub_shift = a.pt.sub_bits ? (uint32_t)(64 - a.pt.sub_bits) : 0u;
   for (uint32_t sub = 0; sub <= sub_mask; ++sub) {
@@ -797,11 +834,12 @@ int gop_of(int32_t val_dtype, int32_t op) {
   return -1;
 }
 
-template <int KD, int VD, bool PART>
+// PATH: 0 direct, 1 partitioned, 2 direct for float sums of few groups (accumulator copies)
+template <int KD, int VD, int PATH>
 const void* agg_row(int g) {
 #define GB_AGG(GG)                                                                           \
-  (PART ? reinterpret_cast<const void*>(&gb_aggregate_part_kernel<KD, VD, GG>)               \
-        : reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, GG>))
+  (PATH == 1 ? reinterpret_cast<const void*>(&gb_aggregate_part_kernel<KD, VD, GG>)          \
+             : reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, GG, PATH == 2 && GG == G_SUM_F32>))
   if constexpr (VD == AGG_F32) {
     switch (g) {
       case G_COUNT: return GB_AGG(G_COUNT);
@@ -822,19 +860,23 @@ const void* agg_row(int g) {
 #undef GB_AGG
 }
 
-template <int KD, bool PART>
+template <int KD, int PATH>
 const void* agg_kernel_kd(int32_t vd, int g) {
   switch (vd) {
-    case AGG_I32: return agg_row<KD, AGG_I32, PART>(g);
-    case AGG_I64: return agg_row<KD, AGG_I64, PART>(g);
-    case AGG_F32: return agg_row<KD, AGG_F32, PART>(g);
+    case AGG_I32: return agg_row<KD, AGG_I32, PATH>(g);
+    case AGG_I64: return agg_row<KD, AGG_I64, PATH>(g);
+    case AGG_F32: return agg_row<KD, AGG_F32, PATH>(g);
     default: return nullptr;
   }
 }
 
-const void* agg_kernel(int32_t kd, int32_t vd, int g, bool part) {
-  if (kd == AGG_I32) return part ? agg_kernel_kd<AGG_I32, true>(vd, g) : agg_kernel_kd<AGG_I32, false>(vd, g);
-  return part ? agg_kernel_kd<AGG_I64, true>(vd, g) : agg_kernel_kd<AGG_I64, false>(vd, g);
+template <int KD>
+const void* agg_kernel_path(int32_t vd, int g, int path) {
+  return path == 1 ? agg_kernel_kd<KD, 1>(vd, g) : path == 2 ? agg_kernel_kd<KD, 2>(vd, g) : agg_kernel_kd<KD, 0>(vd, g);
+}
+
+const void* agg_kernel(int32_t kd, int32_t vd, int g, int path) {
+  return kd == AGG_I32 ? agg_kernel_path<AGG_I32>(vd, g, path) : agg_kernel_path<AGG_I64>(vd, g, path);
 }
 
 template <int KD>
@@ -897,6 +939,7 @@ struct agg_groupby_s {
   void* ws = nullptr;
   Table t{};
   Part pt{};           // bits == 0: the direct path
+  int path = 0;        // 0 direct, 1 partitioned, 2 direct for float sums of few groups
   int agg_blocks = 1;  // aggregation workgroups resident per CU
 };
 
@@ -990,7 +1033,8 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   p->max_groups = max_groups;
   // aggregation grids are sized to what the chip holds at once (no second, mostly idle wave of workgroups)
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, agg_kernel(key_dtype, val_dtype, g, bits != 0),
+  p->path = bits ? 1 : (sub_bits == 0 && g == G_SUM_F32 && max_groups <= kFewGroups ? 2 : 0);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, agg_kernel(key_dtype, val_dtype, g, p->path),
                                                    bits ? kPartThreads : kDirectThreads, 0) !=
           hipSuccess ||
       nb < 1) {
@@ -1035,7 +1079,7 @@ int agg_groupby_run(agg_groupby_t p, const void* keys, const void* vals, int64_t
   if (n > 0 && p->pt.bits == 0) {
     const int64_t grid =
         std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, kDirectThreads * 16), (int64_t)cu * p->agg_blocks));
-    rc = launch(agg_kernel(p->key_dtype, p->val_dtype, p->gop, false), (int)grid, kDirectThreads, &a, stream);
+    rc = launch(agg_kernel(p->key_dtype, p->val_dtype, p->gop, p->path), (int)grid, kDirectThreads, &a, stream);
     if (rc != AGG_OK) return rc;
   } else if (n > 0) {
     const int64_t P = (int64_t)1 << p->pt.bits;
@@ -1045,7 +1089,7 @@ int agg_groupby_run(agg_groupby_t p, const void* keys, const void* vals, int64_t
                                                : reinterpret_cast<const void*>(&gb_hist_kernel<AGG_I64>);
     const void* scat = p->key_dtype == AGG_I32 ? scatter_kd<AGG_I32>(p->val_dtype, hasv, p->pt.bits)
                                                : scatter_kd<AGG_I64>(p->val_dtype, hasv, p->pt.bits);
-    const void* aggk = agg_kernel(p->key_dtype, p->val_dtype, p->gop, true);
+    const void* aggk = agg_kernel(p->key_dtype, p->val_dtype, p->gop, 1);
     for (int64_t c0 = 0; c0 < n; c0 += kChunkRows) {
       const int64_t m = std::min<int64_t>(kChunkRows, n - c0);
       a.keys = static_cast<const char*>(keys) + c0 * kw;
