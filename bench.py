@@ -856,19 +856,21 @@ def main():
     if not args.no_e2e:
         settle(torch)
         e2e = {}
+        # every plan (and its staging ring) is made first, and the copy engines
+        # are left a moment to finish clearing new device memory, so that no
+        # timed copy shares them with the driver's clearing
+        plans = {(src, dt): agg.Plan(dt, "sum", max_n=n, src=src)
+                 for src in ("pinned_host", "zerocopy") for dt in DTYPES}
         dst = torch.empty_like(dev["i32"])
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        dst.copy_(host["i32"], non_blocking=True)
-        e1.record(stream)
         torch.cuda.synchronize()
-        h2d = n * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-        e2e["h2d_copy_GB/s"] = round(h2d, 2)
-        del dst
+        time.sleep(2.0)
         for src in ("pinned_host", "zerocopy"):
             for dt in DTYPES:
-                p = agg.Plan(dt, "sum", max_n=n, src=src)
-                p.enqueue(host[dt][: 1 << 24], o, n=1 << 24, stream=stream)  # warm the path
+                p = plans[(src, dt)]
+                # one untimed full run first: after the link has idled, the first 100 ms or so
+                # of host-to-device traffic run slower (measured: 48.5 GB/s for the first staged
+                # scan in a process, 55.9 GB/s for the same scan repeated)
+                p.enqueue(host[dt], o, stream=stream)
                 torch.cuda.synchronize()
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 t0 = time.perf_counter()
@@ -879,9 +881,21 @@ def main():
                 wall_s = time.perf_counter() - t0
                 gbs = n * WIDTH[dt] / (e0.elapsed_time(e1) * 1e-3) / 1e9
                 e2e[f"{src}_{dt}_sum"] = {"GB/s": round(gbs, 2), "pcie_frac": round(gbs / PCIE_PEAK_GBS, 3),
-                                          "h2d_ceiling_frac": round(gbs / h2d, 3),
                                           "wall_ms": round(wall_s * 1e3, 2)}
-                p.close()
+        # the host-to-device ceiling: one plain copy of the int32 column
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dst.copy_(host["i32"], non_blocking=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        h2d = n * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        e2e["h2d_copy_GB/s"] = round(h2d, 2)
+        for k, v in e2e.items():
+            if isinstance(v, dict) and "GB/s" in v:
+                v["h2d_ceiling_frac"] = round(v["GB/s"] / h2d, 3)
+        del dst
+        for p in plans.values():
+            p.close()
         # frame-of-reference + bit-packed int32 (compression cuts the PCIe bytes)
         t0 = time.perf_counter()
         pc = agg.pack_i32(host["i32"].numpy())
