@@ -11,12 +11,14 @@ fraction, the dominant kernel's roofline (HIP events over the timed region),
 the precision report (the three float modes on the precision-study column:
 rel / abs_norm / kappa against the oracle's stored exact sum, and the a-priori
 bound), the fused filter, the 2^20-item int32 SUM (per call, host enqueue and
-GPU time), the Zipf and sorted columns, the paper's SF 50-200 sweep, group-by
+GPU time), other readers of the same column for context (torch's sum, a device
+copy), the Zipf and sorted columns, the paper's SF 50-200 sweep, group-by
 over 2^28 rows, the end-to-end rate from pinned host memory (chunked copy
 pipeline and zero-copy, raw and packed) with the measured host-to-device copy
 ceiling, energy per aggregation, the 4096-column batch, serving (the scaled
-configuration by default, with a sample checked against the same requests run
-alone), and the CPU oracle's rate (cpu_baseline: the host's CPU share of
+configuration by default at 0.8 of the PCIe-bound load, with a sample checked
+against the same requests run alone, and the same stream at loads 0.5 and 0.95),
+and the CPU oracle's rate (cpu_baseline: the host's CPU share of
 threads, one thread, and the host memory read ceiling).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
@@ -411,10 +413,10 @@ def bench_groupby(agg, torch, stream, dev):
     return out
 
 
-def bench_serve(agg, torch, host_i32, dev_i32, full=False):
+def bench_serve(agg, torch, host_i32, dev_i32, full=False, rho=0.8):
     """Poisson stream of int32 requests, lengths log-uniform in [1e4, n_max],
     30% resident (slices of a column in HBM) and 70% shipped from pinned host
-    memory, admitted by a 200 GB HBM budget, at 0.8 of the PCIe-bound capacity."""
+    memory, admitted by a 200 GB HBM budget, at rho of the PCIe-bound capacity."""
     from datagen.serving import mean_bytes, request_stream
     nreq, n_max = (10_000, 1 << 33) if full else (1000, 1 << 30)
     arena_h = host_i32
@@ -424,7 +426,7 @@ def bench_serve(agg, torch, host_i32, dev_i32, full=False):
         datagen.fill_ptr(arena_h.data_ptr(), n_max, "i32", "uniform", 13)
         log(f"serving arena: {n_max} int32 items in pinned host memory")
     cap = 55e9 / (0.7 * mean_bytes(10_000, n_max, 4))
-    rate = 0.8 * cap
+    rate = rho * cap
     specs = request_stream(nreq, seed=13, n_min=10_000, n_max=n_max, rate_per_s=rate, resident_frac=0.3,
                            hot_items=dev_i32.numel(), arena_items=arena_h.numel())
     reqs = [dict(ptr=(dev_i32 if s["resident"] else arena_h).data_ptr() + 4 * s["offset"], n=s["n"],
@@ -464,7 +466,7 @@ def bench_serve(agg, torch, host_i32, dev_i32, full=False):
             "scaled: 10^3 requests up to 2^30 items (the full 10^4 requests up to 2^33 run with --serve-full "
             "and in tests/test_gpu_serve.py with AGG_SERVE_FULL=1)",
             "checked_vs_alone": len(sample), "mismatches_vs_alone": mism,
-            "requests": nreq, "n_range": [10_000, n_max], "arrival_rate_per_s": round(rate, 1),
+            "requests": nreq, "n_range": [10_000, n_max], "load_rho": rho, "arrival_rate_per_s": round(rate, 1),
             "hbm_budget_bytes": budget, "max_slots": 8, "max_shipping": 2,
             "completed": sm["completed"], "failed": sm["failed"],
             "p50_ms": round(agg.percentile(lat, 50) * 1e3, 3), "p99_ms": round(agg.percentile(lat, 99) * 1e3, 3),
@@ -584,6 +586,36 @@ def bench_sf_sweep(agg, torch, stream, hbuf, dbuf):
                         "GB/s": round(n * 4 / (ms * 1e-3) / 1e9, 1)}
         out[f"SF{sf}"] = rec
     return out
+
+
+def bench_device_reference(torch, dev):
+    """Other readers of the same 2^30-item columns on the same device, for
+    context beside the scan's rate: torch's own sums (read-only reductions;
+    int32 with int64 accumulation, float32) and a device-to-device copy of
+    the int32 column (counted as read + written bytes)."""
+    x = dev["i32"]
+    nbytes = x.numel() * 4
+
+    def timed(f, reps=5):
+        f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_sum = timed(lambda: torch.sum(x, dtype=torch.int64))
+    ms_fsum = timed(lambda: torch.sum(dev["f32"]))
+    y = torch.empty_like(x)
+    ms_copy = timed(lambda: y.copy_(x))
+    del y
+    return {"torch_sum_i32_GB/s": round(nbytes / (ms_sum * 1e-3) / 1e9, 1),
+            "torch_sum_f32_GB/s": round(nbytes / (ms_fsum * 1e-3) / 1e9, 1),
+            "d2d_copy_read_plus_write_GB/s": round(2 * nbytes / (ms_copy * 1e-3) / 1e9, 1),
+            "note": "same device and column, other kernels: context for the scan's fraction of the 8 TB/s peak"}
 
 
 def bench_small_call(agg, torch, stream, dev_i32):
@@ -838,6 +870,7 @@ def main():
     c1 = bench_small_call(agg, torch, stream, dev["i32"])
     extra["i32_sum_2e20_us_per_call"] = c1["us_per_call_back_to_back"]
     extra["i32_sum_2e20"] = c1
+    extra["device_reference"] = bench_device_reference(torch, dev)
 
     # ---- the other distributions and the paper's SF sweep (one spare 8 GiB buffer on each side)
     if not args.no_dists:
@@ -940,6 +973,13 @@ def main():
     if not args.no_serve:
         settle(torch)
         extra["serve"] = bench_serve(agg, torch, host["i32"], dev["i32"], full=args.serve_full)
+        # the same scaled stream at the two other loads of the serving configuration
+        keep = ("load_rho", "arrival_rate_per_s", "completed", "failed", "mismatches_vs_alone", "p50_ms", "p99_ms",
+                "resident_p50_ms", "resident_p99_ms", "shipped_p50_ms", "shipped_p99_ms", "makespan_s",
+                "shipped_GB/s")
+        extra["serve_load_sweep"] = {
+            f"rho_{r}": {k: v for k, v in bench_serve(agg, torch, host["i32"], dev["i32"], rho=r).items() if k in keep}
+            for r in (0.5, 0.95)}
 
     # ---- CPU oracle baseline (rank 0, N = 1): one step's cells on the host cores
     cpu = None
