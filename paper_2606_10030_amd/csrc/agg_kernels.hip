@@ -181,6 +181,12 @@ __global__ void __launch_bounds__(1024) batch_scan_kernel(BatchArgs a) {
       w0 = rec[0];
       w1 = rec[1];
     }
+    // The records are read once per 64 items; passing them through an empty
+    // asm makes the wait for their loads happen here, once.  Otherwise the
+    // registers still count as loaded at the top of the item loop below, and
+    // every item began with a wait for all of the wave's memory operations
+    // (the previous item's partial store included): a round trip per item.
+    __asm__ volatile("" : "+v"(w0), "+v"(w1));
     const int64_t left = (a.nitems - base + nwaves - 1) / nwaves;
     const int cnt = left < kWave ? (int)left : kWave;
     for (int l = 0; l < cnt; ++l) {
