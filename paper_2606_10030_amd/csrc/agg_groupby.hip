@@ -613,10 +613,12 @@ struct LdsTable {
               int dk;
               int64_t dlo, dhi;
               f32_digits(fvv[r], &dk, &dlo, &dhi);
-              if (dlo) at_add<true>(reinterpret_cast<unsigned long long*>(&dig[s * kLdsDigits + dk - 1]),
-                                    (unsigned long long)dlo);
-              if (dhi) at_add<true>(reinterpret_cast<unsigned long long*>(&dig[s * kLdsDigits + dk]),
-                                    (unsigned long long)dhi);
+              // both adds unconditionally (no branch per digit): a float the slot
+              // holds has 1 <= dk <= 6, and a zero (dk = 0, both digits 0) adds 0
+              // to digit slots 0 and 1
+              const int j = dk > 0 ? dk - 1 : 0;
+              at_add<true>(reinterpret_cast<unsigned long long*>(&dig[s * kLdsDigits + j]), (unsigned long long)dlo);
+              at_add<true>(reinterpret_cast<unsigned long long*>(&dig[s * kLdsDigits + j + 1]), (unsigned long long)dhi);
             }
           } else {
             apply<G, true>(&cnt[s], &val[kVal ? s : 0], &dig[0], &flags[0], ivv[r], fvv[r]);
