@@ -553,7 +553,10 @@ struct LdsTable {
   // Rows first, first + step, ... below last whose key hash has the bits
   // (hash >> sub_shift) & sub_mask equal to sub; a row whose key finds no
   // slot within kLdsProbes goes to the global table.
-  template <int VD, bool ROWS = false>  // ROWS: keys holds staged (key, value) records
+  // ROWS: keys holds staged (key, value) records.  SUB: the plan has
+  // sub-partition passes (else every row belongs to the single pass and the
+  // per-row test of its hash bits is left out)
+  template <int VD, bool ROWS = false, bool SUB = true>
   __device__ __forceinline__ void fold_rows(const Table& t, const void* keys, const void* vals, int64_t first, int64_t last,
                             int64_t step, uint32_t sub_shift, uint32_t sub_mask, uint32_t sub) {
     constexpr int R = kAggRows;
@@ -599,7 +602,7 @@ struct LdsTable {
         if (base + r * step >= last) break;
         const KT k = (KT)kk[r];
         const uint64_t hk = key_hash<KD>(kk[r]);
-        if (((uint32_t)(hk >> sub_shift) & sub_mask) != sub) continue;  // another pass's row
+        if (SUB && ((uint32_t)(hk >> sub_shift) & sub_mask) != sub) continue;  // another pass's row
         bool in_lds = true;
         if constexpr (kDig) in_lds = lds_digits_hold(fvv[r]);
         const int slot = in_lds ? slot_of(k, hk) : -1;  // outside the LDS slot's digits: the global table
@@ -684,7 +687,7 @@ constexpr int kFewSlots = 256;
 // Direct path: every workgroup sweeps the rows grid-stride into one LDS
 // table, in 2^sub_bits passes (each taking the keys of one sub-partition:
 // the top bits of the key's hash) when the groups need more than one table.
-template <int KD, int VD, int G, bool FEW>
+template <int KD, int VD, int G, bool FEW, bool SUB>
 __global__ void __launch_bounds__(kDirectThreads) gb_aggregate_kernel(Args a) {
   static_assert(!FEW || G == G_SUM_F32, "the few-groups table is for float sums");
   __shared__ LdsTable<G, KD, FEW ? kFewSlots : lds_slots<G, KD>(), kDirectThreads, FEW ? kFewCopies : 1> tab;
@@ -693,8 +696,8 @@ __global__ void __launch_bounds__(kDirectThreads) gb_aggregate_kernel(Args a) {
   for (uint32_t sub = 0; sub <= sub_mask; ++sub) {
     tab.clear();
     __syncthreads();
-    tab.template fold_rows<VD>(a.t, a.keys, a.vals, (int64_t)blockIdx.x * kDirectThreads + threadIdx.x, a.n,
-                               (int64_t)gridDim.x * kDirectThreads, sub_shift, sub_mask, sub);
+    tab.template fold_rows<VD, false, SUB>(a.t, a.keys, a.vals, (int64_t)blockIdx.x * kDirectThreads + threadIdx.x,
+                                           a.n, (int64_t)gridDim.x * kDirectThreads, sub_shift, sub_mask, sub);
     __syncthreads();
     tab.flush(a.t);
     __syncthreads();
@@ -709,7 +712,7 @@ __global__ void __launch_bounds__(kDirectThreads) gb_aggregate_kernel(Args a) {
 // table (more partitions than the scatter takes), its rows are folded in
 // several passes, each taking the rows of one sub-partition (the next bits of
 // the key's hash) and flushing the table after it.
-template <int KD, int VD, int G>
+template <int KD, int VD, int G, bool SUB>
 __global__ void __launch_bounds__(kPartThreads) gb_aggregate_part_kernel(Args a) {
   __shared__ LdsTable<G, KD, lds_slots<G, KD>(), kPartThreads> tab;
   const int P = 1 << a.pt.bits;
@@ -731,8 +734,8 @@ __global__ void __launch_bounds__(kPartThreads) gb_aggregate_part_kernel(Args a)
     for (uint32_t sub = 0; sub <= sub_mask; ++sub) {
       tab.clear();
       __syncthreads();
-      tab.template fold_rows<VD, true>(a.t, a.pt.pk, a.pt.pv, r + threadIdx.x, seg_end, kPartThreads, sub_shift,
-                                       sub_mask, sub);
+      tab.template fold_rows<VD, true, SUB>(a.t, a.pt.pk, a.pt.pv, r + threadIdx.x, seg_end, kPartThreads,
+                                            sub_shift, sub_mask, sub);
       __syncthreads();
       tab.flush(a.t);
       __syncthreads();
@@ -836,12 +839,16 @@ int gop_of(int32_t val_dtype, int32_t op) {
   return -1;
 }
 
-// PATH: 0 direct, 1 partitioned, 2 direct for float sums of few groups (accumulator copies)
+// PATH: 0 direct, 1 partitioned, 2 direct for float sums of few groups
+// (accumulator copies), 3 direct in sub-partition passes, 4 partitioned in
+// sub-partition passes.  Plans without passes take kernels whose fold has no
+// per-row pass test.
 template <int KD, int VD, int PATH>
 const void* agg_row(int g) {
-#define GB_AGG(GG)                                                                           \
-  (PATH == 1 ? reinterpret_cast<const void*>(&gb_aggregate_part_kernel<KD, VD, GG>)          \
-             : reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, GG, PATH == 2 && GG == G_SUM_F32>))
+#define GB_AGG(GG)                                                                                        \
+  (PATH == 1 || PATH == 4                                                                                 \
+       ? reinterpret_cast<const void*>(&gb_aggregate_part_kernel<KD, VD, GG, PATH == 4>)                  \
+       : reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, GG, PATH == 2 && GG == G_SUM_F32, PATH == 3>))
   if constexpr (VD == AGG_F32) {
     switch (g) {
       case G_COUNT: return GB_AGG(G_COUNT);
@@ -874,7 +881,13 @@ const void* agg_kernel_kd(int32_t vd, int g) {
 
 template <int KD>
 const void* agg_kernel_path(int32_t vd, int g, int path) {
-  return path == 1 ? agg_kernel_kd<KD, 1>(vd, g) : path == 2 ? agg_kernel_kd<KD, 2>(vd, g) : agg_kernel_kd<KD, 0>(vd, g);
+  switch (path) {
+    case 1: return agg_kernel_kd<KD, 1>(vd, g);
+    case 2: return agg_kernel_kd<KD, 2>(vd, g);
+    case 3: return agg_kernel_kd<KD, 3>(vd, g);
+    case 4: return agg_kernel_kd<KD, 4>(vd, g);
+    default: return agg_kernel_kd<KD, 0>(vd, g);
+  }
 }
 
 const void* agg_kernel(int32_t kd, int32_t vd, int g, int path) {
@@ -941,7 +954,7 @@ struct agg_groupby_s {
   void* ws = nullptr;
   Table t{};
   Part pt{};           // bits == 0: the direct path
-  int path = 0;        // 0 direct, 1 partitioned, 2 direct for float sums of few groups
+  int path = 0;        // 0 direct, 1 partitioned, 2 few-groups float sums, 3 / 4: 0 / 1 in sub-partition passes
   int agg_blocks = 1;  // aggregation workgroups resident per CU
 };
 
@@ -1035,7 +1048,8 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   p->max_groups = max_groups;
   // aggregation grids are sized to what the chip holds at once (no second, mostly idle wave of workgroups)
   int nb = 0;
-  p->path = bits ? 1 : (sub_bits == 0 && g == G_SUM_F32 && max_groups <= kFewGroups ? 2 : 0);
+  p->path = bits ? (sub_bits ? 4 : 1)
+                 : sub_bits ? 3 : (g == G_SUM_F32 && max_groups <= kFewGroups ? 2 : 0);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, agg_kernel(key_dtype, val_dtype, g, p->path),
                                                    bits ? kPartThreads : kDirectThreads, 0) !=
           hipSuccess ||
@@ -1091,7 +1105,7 @@ int agg_groupby_run(agg_groupby_t p, const void* keys, const void* vals, int64_t
                                                : reinterpret_cast<const void*>(&gb_hist_kernel<AGG_I64>);
     const void* scat = p->key_dtype == AGG_I32 ? scatter_kd<AGG_I32>(p->val_dtype, hasv, p->pt.bits)
                                                : scatter_kd<AGG_I64>(p->val_dtype, hasv, p->pt.bits);
-    const void* aggk = agg_kernel(p->key_dtype, p->val_dtype, p->gop, 1);
+    const void* aggk = agg_kernel(p->key_dtype, p->val_dtype, p->gop, p->path);
     for (int64_t c0 = 0; c0 < n; c0 += kChunkRows) {
       const int64_t m = std::min<int64_t>(kChunkRows, n - c0);
       a.keys = static_cast<const char*>(keys) + c0 * kw;
