@@ -621,8 +621,9 @@ def bench_device_reference(torch, dev):
 def bench_small_call(agg, torch, stream, dev_i32):
     """The 2^20-item int32 SUM (launch-bound): time per call back to back on
     one stream, the host's enqueue time per call (Python binding + library),
-    and the GPU's own time per call, measured with the calls queued behind
-    enough earlier work that the host is never the limit."""
+    the GPU's own time per call, measured with the calls queued behind
+    enough earlier work that the host is never the limit, and the latency of
+    one call (enqueue, then wait for the stream) with nothing else queued."""
     small = dev_i32[: 1 << 20]
     p = agg.Plan("i32", "sum", max_n=1 << 20)
     o = torch.zeros(32, dtype=torch.uint8, device="cuda")
@@ -651,12 +652,24 @@ def bench_small_call(agg, torch, stream, dev_i32):
     e3.record(stream)
     torch.cuda.synchronize()
     gpu_us = e2.elapsed_time(e3) / calls * 1e3
+    lat = []
+    for _ in range(300):
+        t1 = time.perf_counter()
+        p.enqueue(small, o, stream=stream)
+        stream.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e6)
+    lat.sort()
     pb.close()
     p.close()
     return {"us_per_call_back_to_back": round(back_to_back_us, 2),
             "host_enqueue_us_per_call": round(host_s / calls * 1e6, 2),
             "gpu_us_per_call_queued": round(gpu_us, 2),
-            "note": "gpu_us_per_call_queued: events around calls queued behind ~30 ms of earlier scans"}
+            "latency_us_p50": round(lat[len(lat) // 2], 2),
+            "latency_us_p99": round(lat[int(len(lat) * 0.99)], 2),
+            "launches_per_call": 1,
+            "note": "one launch per call at this size (the scan's last workgroup merges the 256 partials); "
+                    "gpu_us_per_call_queued: events around calls queued behind ~30 ms of earlier scans; "
+                    "latency: enqueue then stream synchronize, 300 calls"}
 
 
 def cpu_model() -> str:

@@ -158,7 +158,8 @@ int agg_default_tune(int32_t dtype, int32_t op, int32_t prec, int64_t n, int32_t
 /* ---- single column (agg_plan / agg_run) ---- */
 
 /* Create a plan for columns of up to max_n items.  Allocates the device
- * workspace (segment partials, 64 KiB; plus
+ * workspace (segment partials, filtered-run counts and two zeroed words,
+ * 128 KiB + 256 B; plus
  * staging_depth * chunk_bytes of device staging, a copy stream and events
  * for PINNED_HOST).  tune == NULL: agg_default_tune for max_n. */
 int agg_plan(agg_plan_t* out, int32_t dtype, int32_t op, int32_t prec, int64_t max_n,
@@ -168,15 +169,20 @@ int agg_plan(agg_plan_t* out, int32_t dtype, int32_t op, int32_t prec, int64_t m
  * the plan's src names, aligned to the item width, with n items readable.
  * out: device memory or page-locked host memory, written by the GPU.
  * Enqueues the scan kernel and the one-workgroup combine kernel (DEVICE,
- * ZEROCOPY), or one copy + scan kernel per chunk and then the combine
+ * ZEROCOPY; a column of at most 1024 segment partials whose scan runs on at
+ * most one workgroup per CU takes the scan launch alone, its last workgroup
+ * merging the partials in the same canonical order, so the result bits are
+ * the same), or one copy + scan kernel per chunk and then the combine
  * (PINNED_HOST); never allocates and never synchronises the stream, so it
- * may be captured into a HIP graph (DEVICE, ZEROCOPY). */
+ * may be captured into a HIP graph (DEVICE, ZEROCOPY).  Calls with one plan
+ * must not overlap (they share its workspace). */
 int agg_run(agg_plan_t plan, const void* col, int64_t n, agg_result* out, void* stream);
 
 /* agg_run without a plan, for callers that cannot allocate (code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation):
- * it allocates nothing, on the device or the host.  The segment partials live
- * in a 64 KiB array in the library's device code, one per device (held until
+ * it allocates nothing, on the device or the host.  The segment partials (and
+ * the single-launch scan's finished-workgroup counter) live in a
+ * 64 KiB + 256 B array in the library's device code, one per device (held until
  * the process ends; agg_init sets it up, else the first call on a device).
  * Same kernels, canonical shape and result bits as agg_run with a plan of the
  * same (dtype, op, prec); launch parameters from agg_default_tune.

@@ -286,10 +286,12 @@ int launch(const void* fn, int grid, int block, void* args, hipStream_t stream) 
 
 }  // namespace agg
 
-// The no-allocation entry point's segment partials (agg_run_noalloc): 64 KiB,
-// the partials of any canonical shape (at most kSegTarget segments).
+// The no-allocation entry point's scratch (agg_run_noalloc): 64 KiB for the
+// partials of any canonical shape (at most kSegTarget segments), then 256
+// bytes whose first word counts the scan's finished workgroups (zero between
+// calls; a device array starts zeroed).
 constexpr int64_t kScratchSlots = kSegTarget;
-static __device__ __align__(256) uint64_t scratch[kScratchSlots];
+static __device__ __align__(256) uint64_t scratch[kScratchSlots + 32];
 
 struct agg_plan_s {
   int device = 0;
@@ -302,6 +304,7 @@ struct agg_plan_s {
   void* ws = nullptr;             // segment partial slots
   uint64_t* part = nullptr;
   uint32_t* err = nullptr;        // packed scans: corrupt-header flag (zero between calls)
+  uint32_t* done = nullptr;       // single-launch scans: finished-workgroup count (zero between calls)
   // pinned-host staging
   int depth = 0;
   int64_t stage_bytes = 0;
@@ -364,11 +367,13 @@ int alloc_device(void** p, size_t bytes) { return device_alloc(p, bytes); }
   } while (0)
 
 int plan_create(agg_plan_s* p) {
-  // segment partials, selected counts (filtered runs), the packed scan's error word
+  // segment partials, selected counts (filtered runs), the packed scan's error
+  // word and the single-launch scan's workgroup counter (128 bytes apart)
   const size_t ws_bytes = (size_t)kSegTarget * 8 * 2 + 256;
   RET_IF(alloc_device(&p->ws, ws_bytes));
   p->part = static_cast<uint64_t*>(p->ws);
   p->err = reinterpret_cast<uint32_t*>(static_cast<char*>(p->ws) + (size_t)kSegTarget * 8 * 2);
+  p->done = reinterpret_cast<uint32_t*>(static_cast<char*>(p->ws) + (size_t)kSegTarget * 8 * 2 + 128);
   HIPCHK(hipMemset(p->ws, 0, ws_bytes));
   if (p->src == AGG_SRC_PINNED_HOST) {
     agg_shape s;
@@ -434,12 +439,22 @@ int batch_capture(agg_batch_s* b, const agg_tune& t) {
   return AGG_OK;
 }
 
+// Small columns take one launch: the scan's last workgroup merges, which
+// saves the host one kernel launch (about 3 us of the call).  Only where the
+// merge is one round trip of device-scope loads (at most 1024 partials: 16
+// loads in flight per lane on a one-wave workgroup) and the finished-
+// workgroup counter sees at most one increment per CU; beyond that the
+// coherent merge rounds and the contended counter cost the GPU more than the
+// separate merge launch (measured up to 2^26 items).
+constexpr int64_t kFuseMaxPartials = 1024;
+
 // The scan of a column the kernels can read directly (device memory, or
-// page-locked host memory read over PCIe) and the combine, with `part` as
-// the segment-partial scratch (kSegTarget 8-byte slots).  Shared by agg_run
-// and agg_run_noalloc; the caller has validated everything.
+// page-locked host memory read over PCIe) and the combine (in the same
+// launch for small columns), with `part` as the segment-partial scratch
+// (kSegTarget 8-byte slots) and `done` as its zeroed workgroup counter.
+// Shared by agg_run and agg_run_noalloc; the caller has validated everything.
 int enqueue_resident(int kind, int32_t dtype, int32_t op, int32_t prec, const agg_tune& t, int cu, const void* col,
-                     int64_t n, agg_result* out, uint64_t* part, hipStream_t stream) {
+                     int64_t n, agg_result* out, uint64_t* part, uint32_t* done, hipStream_t stream) {
   agg_shape s;
   shape_of(dtype, n, &s);
   const bool is_float_sum = dtype == AGG_F32 && (op == AGG_SUM || op == AGG_AVG);
@@ -454,7 +469,9 @@ int enqueue_resident(int kind, int32_t dtype, int32_t op, int32_t prec, const ag
   if (!combine_fn) return AGG_E_INVALID;
   if (s.nseg > 0) {
     const bool aligned = (reinterpret_cast<uintptr_t>(col) & 15) == 0;
-    const void* fn = scan_kernel_ptr(kind, t.unroll, t.nontemporal != 0, aligned);
+    const int grid = grid_for(t, cu, s.nseg);
+    const bool fused = s.nseg <= kFuseMaxPartials && grid <= cu;
+    const void* fn = scan_kernel_ptr(kind, t.unroll, t.nontemporal != 0, aligned, fused);
     if (!fn) return AGG_E_INVALID;
     ScanArgs a;
     a.base = static_cast<const char*>(col);
@@ -464,7 +481,12 @@ int enqueue_resident(int kind, int32_t dtype, int32_t op, int32_t prec, const ag
     a.seg_hi = s.nseg;
     a.base_seg = 0;
     a.part = part;
-    RET_IF(launch(fn, grid_for(t, cu, s.nseg), 64 * t.waves_per_block, &a, stream));
+    if (fused) {
+      a.done = done;
+      a.fin = c;
+      return launch(fn, grid, 64 * t.waves_per_block, &a, stream);
+    }
+    RET_IF(launch(fn, grid, 64 * t.waves_per_block, &a, stream));
   }
   return launch(combine_fn, 1, kCombineThreads, &c, stream);
 }
@@ -603,7 +625,7 @@ int agg_run(agg_plan_t p, const void* col, int64_t n, agg_result* out, void* str
   if (!combine_fn) return AGG_E_INVALID;
 
   if (p->src != AGG_SRC_PINNED_HOST || n == 0)
-    return enqueue_resident(p->kind, p->dtype, p->op, p->prec, t, cu, col, n, out, p->part, stream);
+    return enqueue_resident(p->kind, p->dtype, p->op, p->prec, t, cu, col, n, out, p->part, p->done, stream);
 
   // Pinned host: copy chunks of whole segments into the staging ring on the
   // copy stream while the scan of earlier chunks runs on `stream`.
@@ -653,7 +675,7 @@ int agg_run_noalloc(int32_t dtype, int32_t op, int32_t prec, int32_t src, const 
   agg_tune t;
   tune_for(kind, src, n * w, &t);
   return enqueue_resident(kind, dtype, op, prec, t, g_dev[dev].cu, col, n, out, part,
-                          static_cast<hipStream_t>(stream_v));
+                          reinterpret_cast<uint32_t*>(part + kScratchSlots), static_cast<hipStream_t>(stream_v));
 }
 
 namespace {

@@ -439,29 +439,88 @@ struct PartMerge {
 // (w0 + w1) + (w2 + w3).  A workgroup of any size runs it (each physical wave
 // takes virtual waves w, w + W, ...), so the bits do not depend on the block
 // size.  Every thread of the workgroup must call it; thread 0 gets the total.
-template <int K>
+// COHERENT: the partials were stored in the same launch by other workgroups,
+// so each is read with a device-scope load (served from the level every XCD
+// sees rather than from this XCD's L2; about a microsecond per round trip).
+template <bool COHERENT, typename P>
+__device__ __forceinline__ P load_partial(const P* p) {
+  if constexpr (COHERENT)
+    return __hip_atomic_load(const_cast<P*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    return *p;
+}
+
+// M virtual waves (vw0, vw0 + stride, ...; those >= 4 are skipped) folded by
+// one physical wave at once.  Each round issues all of its loads before it
+// merges any (16 per lane: B per virtual wave), predicated on the index, so
+// a short tail costs one round trip like a full round; the merges then run
+// in each virtual lane's canonical order.  Indices are 32-bit (a column has
+// at most kSegTarget partials).
+template <int K, bool COHERENT, int M>
+__device__ __forceinline__ void fold_virtual_waves(const typename Fold<K>::part* __restrict__ part, int nseg,
+                                                   int vw0, int stride, int lane, typename Fold<K>::part* lds) {
+  using F = Fold<K>;
+  using P = typename F::part;
+  constexpr int kVirtualWaves = kCombineLanes / kWave;
+  constexpr int B = 16 / M;
+  P acc[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) acc[m] = F::pidentity();
+  for (int k0 = 0; k0 < nseg; k0 += B * kCombineLanes) {
+    P v[M][B];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int vw = vw0 + m * stride;
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int i = k0 + b * kCombineLanes + vw * kWave + lane;
+        if (vw < kVirtualWaves && i < nseg) v[m][b] = load_partial<COHERENT>(part + i);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int vw = vw0 + m * stride;
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int i = k0 + b * kCombineLanes + vw * kWave + lane;
+        if (vw < kVirtualWaves && i < nseg) acc[m] = F::pmerge(acc[m], v[m][b]);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int vw = vw0 + m * stride;
+    if (vw < kVirtualWaves) {
+      const P t = wave_reduce(acc[m], PartMerge<K>());
+      if (lane == 0) lds[vw] = t;
+    }
+  }
+}
+
+template <int K, bool COHERENT = false>
 __device__ typename Fold<K>::part combine_partials(const typename Fold<K>::part* __restrict__ part,
-                                                   int64_t nseg) {
+                                                   int64_t nseg64) {
   using F = Fold<K>;
   using P = typename F::part;
   constexpr int kVirtualWaves = kCombineLanes / kWave;
   __shared__ P lds[kVirtualWaves];
+  const int nseg = (int)nseg64;
   const int lane = threadIdx.x & (kWave - 1);
   const int W = blockDim.x / kWave;
-  for (int vw = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); vw < kVirtualWaves; vw += W) {
-    P acc = F::pidentity();
-    int64_t k = vw * kWave + lane;
-    constexpr int B = 16;
-    for (; k + (B - 1) * kCombineLanes < nseg; k += B * kCombineLanes) {
-      P v[B];
-#pragma unroll
-      for (int b = 0; b < B; ++b) v[b] = part[k + b * kCombineLanes];
-#pragma unroll
-      for (int b = 0; b < B; ++b) acc = F::pmerge(acc, v[b]);
-    }
-    for (; k < nseg; k += kCombineLanes) acc = F::pmerge(acc, part[k]);
-    acc = wave_reduce(acc, PartMerge<K>());
-    if (lane == 0) lds[vw] = acc;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if constexpr (!COHERENT) {
+    // the merge launches: four-wave workgroups, one virtual wave each
+    for (int vw = w; vw < kVirtualWaves; vw += W) fold_virtual_waves<K, false, 1>(part, nseg, vw, W, lane, lds);
+  } else if (w < kVirtualWaves) {
+    // the in-launch merge runs on the scan's workgroup: a wave takes virtual
+    // waves w, w + W, ... at once (four with one wave per workgroup, at most
+    // two with two or three, one with four or more)
+    if (W == 1)
+      fold_virtual_waves<K, true, 4>(part, nseg, w, W, lane, lds);
+    else if (W < kVirtualWaves)
+      fold_virtual_waves<K, true, 2>(part, nseg, w, W, lane, lds);
+    else
+      fold_virtual_waves<K, true, 1>(part, nseg, w, W, lane, lds);
   }
   __syncthreads();
   P total = F::pidentity();

@@ -19,16 +19,6 @@ enum Kind : int {
   K_NUM
 };
 
-// One launch of the single-column scan over segments [seg_lo, seg_hi).
-struct ScanArgs {
-  const char* base;      // address of segment base_seg of the column
-  int64_t col_bytes;     // n * width
-  int64_t seg_bytes;     // canonical segment size
-  int64_t seg_lo, seg_hi;
-  int64_t base_seg;      // segment index that `base` points at
-  void* part;            // segment partials (8-byte slots), indexed by segment
-};
-
 // The single-column merge of all segment partials.
 struct CombineArgs {
   const void* part;
@@ -38,6 +28,21 @@ struct CombineArgs {
   int32_t is_avg;
   int32_t prec_used;
   uint32_t* err = nullptr;  // packed scans: nonzero if a corrupt block header was seen (read, then cleared)
+};
+
+// One launch of the single-column scan over segments [seg_lo, seg_hi).
+struct ScanArgs {
+  const char* base;      // address of segment base_seg of the column
+  int64_t col_bytes;     // n * width
+  int64_t seg_bytes;     // canonical segment size
+  int64_t seg_lo, seg_hi;
+  int64_t base_seg;      // segment index that `base` points at
+  void* part;            // segment partials (8-byte slots), indexed by segment
+  // Single-launch form (the launch covers every segment): a zeroed counter
+  // of finished workgroups; the last one merges the partials as `fin` says
+  // and zeroes the counter again.  nullptr: a separate combine launch follows.
+  uint32_t* done = nullptr;
+  CombineArgs fin{};
 };
 
 // One launch of the packed-column scan: each wave folds blocks wave,
@@ -145,7 +150,8 @@ bool tune_is_valid(const agg_tune& t);
 bool tune_cache_lookup(int kind, int32_t src, int64_t bytes, agg_tune* out);
 void builtin_tune_for(int kind, agg_tune* out);
 
-const void* scan_kernel_ptr(int kind, int unroll, bool nontemporal, bool aligned);
+// fused: the single-launch form (ScanArgs::done set)
+const void* scan_kernel_ptr(int kind, int unroll, bool nontemporal, bool aligned, bool fused = false);
 const void* combine_kernel_ptr(int kind);
 const void* packed_scan_kernel_ptr(int kind);   // K_SUM_I32, K_MIN_I32, K_MAX_I32
 const void* filter_scan_kernel_ptr(int kind, int32_t filter_dtype, bool aligned);

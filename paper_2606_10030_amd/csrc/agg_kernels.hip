@@ -5,10 +5,14 @@
 // reduction.  Pass 1: each wave folds whole segments of the column (see
 // fold_segment) and stores one partial per segment.  Pass 2: one workgroup
 // merges the segment partials in the canonical order and writes the result.
-// No atomics and no fences: the merge order is fixed, so the result is
-// deterministic (the property the paper's FPGA design gets from its static
-// reduction tree), and the launch boundary is the global synchronisation the
-// paper's fused kernel takes from cooperative groups.
+// The merge order is fixed, so the result is deterministic (the property the
+// paper's FPGA design gets from its static reduction tree).  Pass 2 runs
+// as its own launch (the launch boundary is the global synchronisation) or,
+// for a small column scanned in one launch, inside it: the workgroup that
+// finishes last merges, which saves the host a kernel launch (the paper's
+// fused kernel takes a cooperative-groups grid barrier for this; a counter
+// of finished workgroups needs no co-resident grid).  Both forms run the same
+// merge, so their results are equal bit for bit.
 //
 // batch_scan_kernel / batch_combine_kernel: many columns of mixed type and
 // function in one persistent launch; the same segment fold and the same
@@ -21,7 +25,48 @@
 
 namespace agg {
 
-template <int K, int U, bool NT, bool AL>
+// Pass 2: merge the segment partials in the canonical order and write the
+// result (every thread of the workgroup calls it).
+template <int K, bool COHERENT = false>
+__device__ __forceinline__ void combine_and_write(const CombineArgs& a) {
+  using P = typename Fold<K>::part;
+  const P total = combine_partials<K, COHERENT>(reinterpret_cast<const P*>(a.part), a.nseg);
+  if (threadIdx.x == 0) {
+    agg_result r = finalize<K>(total, a.n, a.is_avg != 0, a.prec_used);
+    if (a.err) {  // a packed column with a corrupt block header: the result is marked invalid
+      if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) r.is_null = -1;
+      __hip_atomic_store(a.err, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // ready for the next call
+    }
+    *a.out = r;
+  }
+}
+
+// Pass 2 inside the scan launch.  The partials are stored with device-scope
+// stores (written through to the level every XCD sees), and each wave waits
+// for its stores to complete before the workgroup counts itself finished;
+// the workgroup whose count completes the grid reads the partials with
+// device-scope loads, merges, and zeroes the counter for the next launch.
+// Fences would cost more than the combine launch they replace: a device-scope
+// release fence in every wave writes back its XCD's whole L2 (2.5% slower at
+// 2^30 items, measured), and an acquire in every wave also invalidates the
+// L2 under the loads other waves still have in flight (4% slower).  Every
+// workgroup reaches this point, so the count always completes.
+template <int K>
+__device__ __forceinline__ void finish_if_last(const CombineArgs& c, uint32_t* done) {
+  __shared__ uint32_t last;
+  __builtin_amdgcn_s_waitcnt(0);  // every memory operation of this wave has completed
+  __syncthreads();
+  if (threadIdx.x == 0)
+    last = __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  combine_and_write<K, true>(c);
+  if (threadIdx.x == 0) __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// FUSED: the single-launch form (a.done set); a separate instance, so the
+// two-launch kernels' fold loop compiles exactly as without the merge.
+template <int K, int U, bool NT, bool AL, bool FUSED>
 __global__ void __launch_bounds__(1024) scan_kernel(ScanArgs a) {
   using F = Fold<K>;
   using P = typename F::part;
@@ -38,25 +83,20 @@ __global__ void __launch_bounds__(1024) scan_kernel(ScanArgs a) {
     const char* seg = a.base + (j - a.base_seg) * a.seg_bytes;
     typename F::acc acc = fold_segment<K, U, NT, AL>(seg, valid, lane);
     acc = wave_reduce(acc, AccMerge<K>());
-    if (lane == 0) part[j] = F::to_part(acc);
+    if (lane == 0) {
+      if constexpr (FUSED)  // a device-scope store: the in-launch merge reads it from another XCD
+        __hip_atomic_store(part + j, F::to_part(acc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else
+        part[j] = F::to_part(acc);
+    }
   }
+  if constexpr (FUSED) finish_if_last<K>(a.fin, a.done);
 }
 
-// Second pass: one workgroup merges the nseg segment partials in the
-// canonical order and writes the result.  The kernel boundary after the
-// scan launches is the global synchronisation: no fences, no atomics.
+// Pass 2 as its own launch: one workgroup.
 template <int K>
 __global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
-  using P = typename Fold<K>::part;
-  const P total = combine_partials<K>(reinterpret_cast<const P*>(a.part), a.nseg);
-  if (threadIdx.x == 0) {
-    agg_result r = finalize<K>(total, a.n, a.is_avg != 0, a.prec_used);
-    if (a.err) {  // a packed column with a corrupt block header: the result is marked invalid
-      if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) r.is_null = -1;
-      __hip_atomic_store(a.err, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // ready for the next call
-    }
-    *a.out = r;
-  }
+  combine_and_write<K>(a);
 }
 
 // ------------------------------------------------------------ packed columns
@@ -258,36 +298,40 @@ namespace {
 
 template <int K>
 struct ScanRow {
-  // [unroll index][nontemporal][aligned]; the unaligned variant is one
-  // (U = 4, temporal) kernel, shared by every entry.
-  static const void* get(int ui, bool nt, bool al) {
-    if (!al) return reinterpret_cast<const void*>(&scan_kernel<K, 4, false, false>);
+  // [fused][unroll index][nontemporal][aligned]; the unaligned variant is
+  // one (U = 4, temporal) kernel per form, shared by every entry.
+  template <bool FU>
+  static const void* get_form(int ui, bool nt, bool al) {
+    if (!al) return reinterpret_cast<const void*>(&scan_kernel<K, 4, false, false, FU>);
     static const void* t[4][2] = {
-        {reinterpret_cast<const void*>(&scan_kernel<K, 4, false, true>),
-         reinterpret_cast<const void*>(&scan_kernel<K, 4, true, true>)},
-        {reinterpret_cast<const void*>(&scan_kernel<K, 8, false, true>),
-         reinterpret_cast<const void*>(&scan_kernel<K, 8, true, true>)},
-        {reinterpret_cast<const void*>(&scan_kernel<K, 16, false, true>),
-         reinterpret_cast<const void*>(&scan_kernel<K, 16, true, true>)},
-        {reinterpret_cast<const void*>(&scan_kernel<K, 32, false, true>),
-         reinterpret_cast<const void*>(&scan_kernel<K, 32, true, true>)}};
+        {reinterpret_cast<const void*>(&scan_kernel<K, 4, false, true, FU>),
+         reinterpret_cast<const void*>(&scan_kernel<K, 4, true, true, FU>)},
+        {reinterpret_cast<const void*>(&scan_kernel<K, 8, false, true, FU>),
+         reinterpret_cast<const void*>(&scan_kernel<K, 8, true, true, FU>)},
+        {reinterpret_cast<const void*>(&scan_kernel<K, 16, false, true, FU>),
+         reinterpret_cast<const void*>(&scan_kernel<K, 16, true, true, FU>)},
+        {reinterpret_cast<const void*>(&scan_kernel<K, 32, false, true, FU>),
+         reinterpret_cast<const void*>(&scan_kernel<K, 32, true, true, FU>)}};
     return t[ui][nt ? 1 : 0];
+  }
+  static const void* get(int ui, bool nt, bool al, bool fused) {
+    return fused ? get_form<true>(ui, nt, al) : get_form<false>(ui, nt, al);
   }
 };
 
 template <int... Ks>
-const void* scan_lookup(int kind, int ui, bool nt, bool al, std::integer_sequence<int, Ks...>) {
+const void* scan_lookup(int kind, int ui, bool nt, bool al, bool fused, std::integer_sequence<int, Ks...>) {
   const void* r = nullptr;
-  ((kind == Ks ? (r = ScanRow<Ks>::get(ui, nt, al), 0) : 0), ...);
+  ((kind == Ks ? (r = ScanRow<Ks>::get(ui, nt, al, fused), 0) : 0), ...);
   return r;
 }
 
 }  // namespace
 
-const void* scan_kernel_ptr(int kind, int unroll, bool nontemporal, bool aligned) {
+const void* scan_kernel_ptr(int kind, int unroll, bool nontemporal, bool aligned, bool fused) {
   const int ui = unroll_index(unroll);
   if (kind < 0 || kind >= K_NUM || ui < 0) return nullptr;
-  return scan_lookup(kind, ui, nontemporal, aligned, std::make_integer_sequence<int, K_NUM>());
+  return scan_lookup(kind, ui, nontemporal, aligned, fused, std::make_integer_sequence<int, K_NUM>());
 }
 
 namespace {

@@ -135,6 +135,43 @@ def test_repeated_runs_are_bitwise_identical(agg):
             assert same_bits(first, plan.run(d))
 
 
+@pytest.mark.parametrize("dtype,op,prec", [("i64", "sum", "neumaier"), ("i32", "min", "neumaier"),
+                                           ("f32", "sum", "neumaier"), ("f32", "avg", "f64_combine")])
+def test_back_to_back_calls_read_their_own_partials(agg, dtype, op, prec):
+    """One plan, 96 calls queued with no synchronisation between them, cycling
+    over three columns and four lengths, under two launch shapes (the second
+    with up to 8192 workgroups): every result is its own column's.  Small
+    columns take one launch whose last workgroup merges partials that other
+    workgroups, on other XCDs, stored in the same launch over the previous
+    call's partials, and the plan's finished-workgroup counter must be zero
+    again after every launch; 2^22 + 7 items take two launches, 2^22 int32 /
+    float32 items (1024 partials on 256 workgroups) one, at the boundary."""
+    import torch
+    n = (1 << 22) + 7
+    cols = [column(dtype, n, seed=300 + i, kind="wide" if dtype == "f32" else "uniform") for i in range(3)]
+    ds = [tdev(c) for c in cols]
+    lens = [n, 1 << 22, (1 << 18) + 7, 1000]
+    calls = 96
+    for t in (None, dict(unroll=8, waves_per_block=4, blocks_per_cu=32, nontemporal=1)):
+        kw = {"tune": agg.make_tune(**t)} if t else {}
+        plan = agg.Plan(dtype, op, max_n=n, prec=prec, **kw)
+        out = torch.zeros((calls, agg.RESULT_BYTES), dtype=torch.uint8, device="cuda")
+        say(f"back-to-back {dtype} {op} {prec} tune {t}")
+        for k in range(calls):
+            plan.enqueue(ds[k % 3], out[k], n=lens[(k // 3) % 4])
+        torch.cuda.synchronize()
+        got = agg.parse_results(out.cpu().numpy().tobytes(), [(plan.dtype, plan.op)] * calls)
+        first = {}
+        for k in range(calls):
+            key = (k % 3, (k // 3) % 4)
+            if key not in first:
+                first[key] = got[k]
+                check(cols[key[0]][:lens[key[1]]], dtype, op, prec, got[k], ctx=f"call {k} tune {t}")
+            else:
+                assert same_bits(first[key], got[k]), f"call {k} (column {key[0]}, length {key[1]}) tune {t}"
+        plan.close()
+
+
 @pytest.mark.parametrize("src", ["pinned_host", "zerocopy"])
 @pytest.mark.parametrize("dtype", ["i32", "i64", "f32"])
 def test_host_sources_match_device(agg, src, dtype):
