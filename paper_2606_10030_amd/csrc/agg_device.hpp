@@ -525,6 +525,9 @@ __device__ typename Fold<K>::part combine_partials(const typename Fold<K>::part*
   __syncthreads();
   P total = F::pidentity();
   if (threadIdx.x == 0) total = F::pmerge(F::pmerge(lds[0], lds[1]), F::pmerge(lds[2], lds[3]));
+  // lds is free again only when thread 0 has read it: a second call in the
+  // same workgroup (the filtered merge takes two) must not overwrite it first
+  __syncthreads();
   return total;
 }
 
