@@ -180,6 +180,29 @@ __device__ __forceinline__ uint32_t part_of(int64_t k, int bits) {
   return (uint32_t)(key_hash<KD>(k) >> (64 - bits));
 }
 
+// The hash placing a key in a few-groups table (256 slots, a single pass):
+// one 32-bit multiply by 2^32 / golden ratio instead of key_hash's wider
+// product.  Bits 24..31 pick the slot, bits 16..23 the probe step (the
+// table reads the slot from the low half and the step from the high half).
+// Where a key lands never shows in a result: only the probe count changes.
+template <int KD>
+__device__ __forceinline__ uint64_t few_hash(int64_t k) {
+  uint32_t x = (uint32_t)k;
+  if constexpr (KD != AGG_I32) x ^= (uint32_t)((uint64_t)k >> 32);
+  const uint32_t h = x * 0x9E3779B1u;
+  return ((uint64_t)(h >> 16) << 32) | (h >> 24);
+}
+
+// 7 * x for x < 2^24 as one full-rate 24-bit multiply (left to itself the
+// compiler issues a quarter-rate 32-bit one for the float-sum slot's digit
+// index).
+static_assert(kLdsDigits == 7, "mul7_u24 scales by the LDS slot's digit count");
+__device__ __forceinline__ uint32_t mul7_u24(uint32_t x) {
+  uint32_t r;
+  __asm__("v_mul_u32_u24 %0, 7, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 // Order-preserving map of non-NaN floats to int32 (and back).
 __device__ __forceinline__ int32_t f32_order(float f) {
   const int32_t b = __float_as_int(f);
@@ -193,15 +216,13 @@ __device__ __forceinline__ void f32_digits(float x, int* k0, int64_t* lo, int64_
   const uint32_t biased = (bits >> 23) & 0xFFu, frac = bits & 0x7FFFFFu;
   const uint64_t m = biased ? (frac | 0x800000u) : frac;
   const int k = biased ? (int)biased - 1 : 0;
-  const uint64_t v = m << (k & 31);
-  int64_t l = (int64_t)(v & 0xFFFFFFFFu), h = (int64_t)(v >> 32);
-  if (bits >> 31) {
-    l = -l;
-    h = -h;
-  }
+  const uint64_t v = m << (k & 31);  // below 2^55
+  // the signed product split as lo + hi * 2^32 with 0 <= lo < 2^32: one
+  // 64-bit negation instead of one per digit (digits may take either sign)
+  const int64_t sv = (bits >> 31) ? -(int64_t)v : (int64_t)v;
   *k0 = k >> 5;
-  *lo = l;
-  *hi = h;
+  *lo = (int64_t)((uint64_t)sv & 0xFFFFFFFFu);
+  *hi = sv >> 32;
 }
 
 template <int KD>
@@ -513,6 +534,7 @@ struct LdsTable {
   static constexpr bool kDig = G == G_SUM_F32;
   static constexpr bool kVal = !kDig && G != G_COUNT;
   static_assert((REP & (REP - 1)) == 0 && REP <= 64, "copies: a power of two, at most a wave");
+  static_assert(REP == 1 || L <= 256, "tables with copies take few_hash's 8 slot bits");
   KT key[L];
   uint32_t cnt[E];  // rows per table stay below 2^32 (a workgroup's share is at most 2^28 rows)
   int64_t val[kVal ? E : 1];
@@ -607,7 +629,7 @@ struct LdsTable {
       for (int r = 0; r < R; ++r) {
         if (base + r * step >= last) break;
         const KT k = b.k[r];
-        const uint64_t hk = key_hash<KD>((int64_t)k);
+        const uint64_t hk = REP > 1 ? few_hash<KD>(k) : key_hash<KD>((int64_t)k);
         if (SUB && ((uint32_t)(hk >> sub_shift) & sub_mask) != sub) continue;  // another pass's row
         const float fv = b.fv[r];
         bool in_lds = true;
@@ -627,8 +649,9 @@ struct LdsTable {
               // holds has 1 <= dk <= 6, and a zero (dk = 0, both digits 0) adds 0
               // to digit slots 0 and 1
               const int j = dk > 0 ? dk - 1 : 0;
-              at_add<true>(reinterpret_cast<unsigned long long*>(&dig[s * kLdsDigits + j]), (unsigned long long)dlo);
-              at_add<true>(reinterpret_cast<unsigned long long*>(&dig[s * kLdsDigits + j + 1]), (unsigned long long)dhi);
+              const int e0 = (int)mul7_u24((uint32_t)s) + j;
+              at_add<true>(reinterpret_cast<unsigned long long*>(&dig[e0]), (unsigned long long)dlo);
+              at_add<true>(reinterpret_cast<unsigned long long*>(&dig[e0 + 1]), (unsigned long long)dhi);
             }
           } else {
             apply<G, true>(&cnt[s], &val[kVal ? s : 0], &dig[0], &flags[0], (int64_t)b.iv[r], fv);
