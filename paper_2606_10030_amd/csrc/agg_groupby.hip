@@ -180,7 +180,7 @@ __device__ __forceinline__ uint32_t part_of(int64_t k, int bits) {
   return (uint32_t)(key_hash<KD>(k) >> (64 - bits));
 }
 
-// The hash placing a key in a few-groups table (256 slots, a single pass):
+// The hash placing a key in a few-groups table (at most 256 slots, a single pass):
 // one 32-bit multiply by 2^32 / golden ratio instead of key_hash's wider
 // product.  Bits 24..31 pick the slot, bits 16..23 the probe step (the
 // table reads the slot from the low half and the step from the high half).
@@ -734,15 +734,19 @@ struct LdsTable {
 // LDS atomics of lanes that meet on a slot serialise (measured on MI355X: a
 // 64-bit add from a wave whose rows spread over 16 slots takes about 24
 // clocks, over 64 addresses 6); a float row makes three (two digits and the
-// count).  A 256-slot table whose slots carry kFewCopies copies of the
+// count).  A small table whose slots carry kFewCopies copies of the
 // accumulators (lane l updates copy l % kFewCopies) cuts the meetings by that
-// factor: 16 groups, 2^28 rows, 0.626 -> 0.594 ms.  For COUNT and integer
+// factor.  16 groups, 2^28 rows: 4 copies of 256 slots 0.626 -> 0.594 ms at
+// one workgroup per CU; at two (the table is 65 KiB) 0.45-0.48 ms with 4
+// copies, 0.44-0.45 with 8 copies of 128 slots and 0.44 with 16 of 64 (the
+// 128-slot table keeps 32 groups a quarter full).  For COUNT and integer
 // values (one or two atomics a row) the smaller table's longer probe chains
-// cost more than the copies save (0.338 -> 0.348 ms, 0.526 -> 0.561 ms), so
-// they keep the full table.
+// cost more than the copies save (0.338 -> 0.348 ms, 0.526 -> 0.561 ms; COUNT
+// with pipelined loads and two workgroups per CU, 0.254 -> 0.246 ms, kept out
+// for a 3% gain), so they keep the full table.
 constexpr int kFewGroups = 32;
-constexpr int kFewCopies = 4;
-constexpr int kFewSlots = 256;
+constexpr int kFewCopies = 8;
+constexpr int kFewSlots = 128;
 
 // Direct path: every workgroup sweeps the rows grid-stride into one LDS
 // table, in 2^sub_bits passes (each taking the keys of one sub-partition:
