@@ -342,13 +342,34 @@ __global__ void __launch_bounds__(kThreads) gb_hist_kernel(Args a) {
   __syncthreads();
   const int64_t lo = (int64_t)blockIdx.x * a.pt.rows_per_wg;
   const int64_t hi = std::min<int64_t>(lo + a.pt.rows_per_wg, a.n);
-  for (int64_t base = lo + threadIdx.x; base < hi; base += kThreads * kAggRows) {
-    int64_t kk[kAggRows];
+  using KT = typename std::conditional<KD == AGG_I32, int32_t, int64_t>::type;
+  auto load = [&](KT* kk, int64_t base) {
 #pragma unroll
-    for (int r = 0; r < kAggRows; ++r) kk[r] = load_key<KD>(a.keys, std::min<int64_t>(base + (int64_t)r * kThreads, hi - 1));
+    for (int r = 0; r < kAggRows; ++r) kk[r] = (KT)load_key<KD>(a.keys, std::min<int64_t>(base + (int64_t)r * kThreads, hi - 1));
+  };
+  auto count = [&](KT* kk, int64_t base) {
+#pragma unroll
+    for (int r = 0; r < kAggRows; ++r) __asm__ volatile("" : "+v"(kk[r]));
 #pragma unroll
     for (int r = 0; r < kAggRows; ++r)
-      if (base + (int64_t)r * kThreads < hi) atomicAdd(&h[part_of<KD>(kk[r], a.pt.bits)], 1u);
+      if (base + (int64_t)r * kThreads < hi) atomicAdd(&h[part_of<KD>((int64_t)kk[r], a.pt.bits)], 1u);
+  };
+  // two batches alternate, so the next batch's loads are in flight while this
+  // one is counted (2^28 rows: 1-3% off the partitioned paths)
+  const int64_t first = lo + threadIdx.x, adv = (int64_t)kThreads * kAggRows;
+  if (first < hi) {
+    KT A[kAggRows], B[kAggRows];
+    load(A, first);
+    for (int64_t base = first;;) {
+      load(B, base + adv);
+      count(A, base);
+      base += adv;
+      if (base >= hi) break;
+      load(A, base + adv);
+      count(B, base);
+      base += adv;
+      if (base >= hi) break;
+    }
   }
   __syncthreads();
   for (int e = threadIdx.x; e < P; e += kThreads) a.pt.hist[(int64_t)e * a.pt.g1 + blockIdx.x] = h[e];
