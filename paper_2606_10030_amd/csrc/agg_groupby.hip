@@ -691,9 +691,9 @@ struct LdsTable {
     // SUM at 1024 groups 1.07 -> 0.99 ms).  Wider rows fold one batch at a
     // time: two batches of int64 values took the fold to 128 registers and
     // ran 5-15% slower.  The few-groups table (REP > 1) runs two workgroups
-    // per CU instead, which needs a single batch's registers.
+    // per CU, which leaves two batches' registers only to COUNT's key-only rows.
     constexpr int kWords = (KD == AGG_I64 ? 2 : 1) + (G == G_COUNT ? 0 : VD == AGG_I64 ? 2 : 1);
-    if constexpr (kWords <= 2 && REP == 1) {
+    if constexpr (kWords <= 2 && (REP == 1 || kWords == 1)) {
       Batch A, B;
       load(A, first);
       for (int64_t base = first;;) {
@@ -760,11 +760,12 @@ struct LdsTable {
 // factor.  16 groups, 2^28 rows: 4 copies of 256 slots 0.626 -> 0.594 ms at
 // one workgroup per CU; at two (the table is 65 KiB) 0.45-0.48 ms with 4
 // copies, 0.44-0.45 with 8 copies of 128 slots and 0.44 with 16 of 64 (the
-// 128-slot table keeps 32 groups a quarter full).  For COUNT and integer
-// values (one or two atomics a row) the smaller table's longer probe chains
-// cost more than the copies save (0.338 -> 0.348 ms, 0.526 -> 0.561 ms; COUNT
-// with pipelined loads and two workgroups per CU, 0.254 -> 0.246 ms, kept out
-// for a 3% gain), so they keep the full table.
+// 128-slot table keeps 32 groups a quarter full).  COUNT takes the same
+// table (4.6 KiB of LDS) with its key loads pipelined and two workgroups per
+// CU: 0.253 -> 0.241 ms at 16 groups, 0.255 -> 0.239 at 32 (at one
+// workgroup per CU and 4 copies it had been slower: 0.338 -> 0.348 ms).
+// Integer sums keep the full table: with copies and two workgroups per CU
+// they ran 0.54 -> 0.64 ms at 16 groups.
 constexpr int kFewGroups = 32;
 constexpr int kFewCopies = 8;
 constexpr int kFewSlots = 128;
@@ -778,7 +779,7 @@ constexpr int kFewSlots = 128;
 template <int KD, int VD, int G, bool FEW, bool SUB>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, kDirectThreads), amdgpu_waves_per_eu(FEW ? 8 : 1)))
 gb_aggregate_kernel(Args a) {
-  static_assert(!FEW || G == G_SUM_F32, "the few-groups table is for float sums");
+  static_assert(!FEW || G == G_SUM_F32 || G == G_COUNT, "the few-groups table is for float sums and counts");
   __shared__ LdsTable<G, KD, FEW ? kFewSlots : lds_slots<G, KD>(), kDirectThreads, FEW ? kFewCopies : 1> tab;
   const uint32_t sub_mask = (1u << a.pt.sub_bits) - 1u;
   const uint32_t sub_shift = a.pt.sub_bits ? (uint32_t)(64 - a.pt.sub_bits) : 0u;
@@ -928,8 +929,8 @@ int gop_of(int32_t val_dtype, int32_t op) {
   return -1;
 }
 
-// PATH: 0 direct, 1 partitioned, 2 direct for float sums of few groups
-// (accumulator copies), 3 direct in sub-partition passes, 4 partitioned in
+// PATH: 0 direct, 1 partitioned, 2 direct for float sums and counts of few
+// groups (accumulator copies), 3 direct in sub-partition passes, 4 partitioned in
 // sub-partition passes.  Plans without passes take kernels whose fold has no
 // per-row pass test.
 template <int KD, int VD, int PATH>
@@ -937,7 +938,7 @@ const void* agg_row(int g) {
 #define GB_AGG(GG)                                                                                        \
   (PATH == 1 || PATH == 4                                                                                 \
        ? reinterpret_cast<const void*>(&gb_aggregate_part_kernel<KD, VD, GG, PATH == 4>)                  \
-       : reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, GG, PATH == 2 && GG == G_SUM_F32, PATH == 3>))
+       : reinterpret_cast<const void*>(&gb_aggregate_kernel<KD, VD, GG, PATH == 2 && (GG == G_SUM_F32 || GG == G_COUNT), PATH == 3>))
   if constexpr (VD == AGG_F32) {
     switch (g) {
       case G_COUNT: return GB_AGG(G_COUNT);
@@ -1143,7 +1144,7 @@ int agg_groupby_plan(agg_groupby_t* out, int32_t key_dtype, int32_t val_dtype, i
   // slower (16 groups, 2^28 rows: 0.555 against 0.526 ms).
   p->path = bits ? (sub_bits ? 4 : 1)
                  : sub_bits ? 3
-                 : max_groups <= kFewGroups ? (g == G_SUM_F32 ? 2 : g == G_SUM_INT ? 3 : 0)
+                 : max_groups <= kFewGroups ? (g == G_SUM_F32 || g == G_COUNT ? 2 : g == G_SUM_INT ? 3 : 0)
                                             : 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, agg_kernel(key_dtype, val_dtype, g, p->path),
                                                    bits ? kPartThreads : kDirectThreads, 0) !=
