@@ -80,7 +80,10 @@ def test_zero_small_and_flags(d2d):
 
 
 def test_float_sums_as_the_gpu_accumulates_them(d2d):
-    """Digits built the way the kernel adds a float (two digits per float)."""
+    """Digits built the way the kernel adds a float (two digits per float: the
+    signed product split as lo + hi * 2^32 with 0 <= lo < 2^32), and built with
+    each digit negated instead (digits of either sign): both round to the exact
+    sum."""
     import numpy as np
     r = random.Random(3)
     for _ in range(300):
@@ -88,6 +91,7 @@ def test_float_sums_as_the_gpu_accumulates_them(d2d):
               np.exp2(np.array([r.randint(-140, 120) for _ in range(50)]))).astype(np.float32)
         xs = xs[np.isfinite(xs)]
         ds = [0] * NDIG
+        dn = [0] * NDIG
         for x in xs.tolist():
             # |x| = mm * 2^(kk - 149): mantissa and exponent from the float's bits
             bits = int(np.float32(abs(x)).view(np.uint32))
@@ -95,10 +99,14 @@ def test_float_sums_as_the_gpu_accumulates_them(d2d):
             mm = (frac | 0x800000) if biased else frac
             kk = biased - 1 if biased else 0
             v = mm << (kk & 31)
+            sv = -v if x < 0 else v
+            ds[kk >> 5] += sv & 0xFFFFFFFF
+            ds[(kk >> 5) + 1] += sv >> 32
             lo, hi = v & 0xFFFFFFFF, v >> 32
             if x < 0:
                 lo, hi = -lo, -hi
-            ds[kk >> 5] += lo
-            ds[(kk >> 5) + 1] += hi
+            dn[kk >> 5] += lo
+            dn[(kk >> 5) + 1] += hi
         want = float(sum((Fraction(float(x)) for x in xs.tolist()), Fraction(0)))
         assert d2d(ds) == want
+        assert d2d(dn) == want
