@@ -716,7 +716,15 @@ struct LdsTable {
   }
 
   __device__ __forceinline__ void flush(const Table& t) {
-    for (int e = threadIdx.x; e <= L; e += NT) {
+    // Every workgroup's table holds its keys in about the same slots (same
+    // hash), so flushing all tables in slot order would have every workgroup
+    // update the same global slots at the same moment, and device-scope
+    // atomics on one address serialise.  Each workgroup starts its pass at
+    // its own offset instead (2^28 rows, 1024 groups: COUNT 0.43 -> 0.39 ms;
+    // the other cases within noise).
+    const int off = (int)(((uint32_t)blockIdx.x * 2654435761u) % (uint32_t)(L + 1));
+    for (int i = threadIdx.x; i <= L; i += NT) {
+      const int e = i + off <= L ? i + off : i + off - (L + 1);
       const KT k = e < L ? key[e] : kMark;
       uint64_t c = 0;
       for (int r = 0; r < REP; ++r) c += cnt[e * REP + r];
