@@ -225,17 +225,6 @@ __device__ __forceinline__ void f32_digits(float x, int* k0, int64_t* lo, int64_
   *hi = sv >> 32;
 }
 
-template <int KD>
-__device__ __forceinline__ int64_t load_key(const void* p, int64_t i) {
-  if constexpr (KD == AGG_I32) return (int64_t) static_cast<const int32_t*>(p)[i];
-  else return static_cast<const int64_t*>(p)[i];
-}
-template <int VD>
-__device__ __forceinline__ int64_t load_ival(const void* p, int64_t i) {
-  if constexpr (VD == AGG_I32) return (int64_t) static_cast<const int32_t*>(p)[i];
-  else return static_cast<const int64_t*>(p)[i];
-}
-
 // Whether an LDS float-sum slot (digits 1..7) can take x.
 __device__ __forceinline__ bool lds_digits_hold(float x) {
   const uint32_t b = __float_as_uint(x);
@@ -343,16 +332,21 @@ __global__ void __launch_bounds__(kThreads) gb_hist_kernel(Args a) {
   const int64_t lo = (int64_t)blockIdx.x * a.pt.rows_per_wg;
   const int64_t hi = std::min<int64_t>(lo + a.pt.rows_per_wg, a.n);
   using KT = typename std::conditional<KD == AGG_I32, int32_t, int64_t>::type;
+  // rows base + r * kThreads: one 64-bit clamp per batch, 32-bit offsets per row
   auto load = [&](KT* kk, int64_t base) {
+    const int64_t b0 = std::min<int64_t>(base, hi - 1);
+    const uint32_t room = (uint32_t)std::min<int64_t>(hi - 1 - b0, (int64_t)kAggRows * kThreads);
 #pragma unroll
-    for (int r = 0; r < kAggRows; ++r) kk[r] = (KT)load_key<KD>(a.keys, std::min<int64_t>(base + (int64_t)r * kThreads, hi - 1));
+    for (int r = 0; r < kAggRows; ++r)
+      kk[r] = (static_cast<const KT*>(a.keys) + b0)[std::min<uint32_t>((uint32_t)(r * kThreads), room)];
   };
   auto count = [&](KT* kk, int64_t base) {
+    const uint32_t left = (uint32_t)std::max<int64_t>(0, std::min<int64_t>(hi - base, (int64_t)kAggRows * kThreads));
 #pragma unroll
     for (int r = 0; r < kAggRows; ++r) __asm__ volatile("" : "+v"(kk[r]));
 #pragma unroll
     for (int r = 0; r < kAggRows; ++r)
-      if (base + (int64_t)r * kThreads < hi) atomicAdd(&h[part_of<KD>((int64_t)kk[r], a.pt.bits)], 1u);
+      if ((uint32_t)(r * kThreads) < left) atomicAdd(&h[part_of<KD>((int64_t)kk[r], a.pt.bits)], 1u);
   };
   // two batches alternate, so the next batch's loads are in flight while this
   // one is counted (2^28 rows: 1-3% off the partitioned paths)
@@ -610,31 +604,39 @@ struct LdsTable {
       float fv[R];
     };
     // rows past the end re-load the last row (in bounds, never folded): no
-    // branch around the loads, so all of them issue before the first wait
+    // branch around the loads, so all of them issue before the first wait.
+    // The batch's rows are base + r * step: one 64-bit clamp per batch, then
+    // 32-bit offsets (R * step < 2^31), so a row's address costs a min and one
+    // 64-bit add instead of a 64-bit compare, two selects and three adds
+    const uint32_t step32 = (uint32_t)step;
     auto load = [&](Batch& b, int64_t base) {
+      const int64_t b0 = std::min<int64_t>(base, last - 1);
+      const uint32_t room = (uint32_t)std::min<int64_t>(last - 1 - b0, (int64_t)R * step);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int64_t i = std::min<int64_t>(base + r * step, last - 1);
+        const uint32_t rel = std::min<uint32_t>((uint32_t)r * step32, room);
         b.iv[r] = 0;
         b.fv[r] = 0.0f;
         if constexpr (ROWS && G != G_COUNT) {
           using SR = StagedRow<KD, VD == AGG_I64 ? AGG_I64 : AGG_I32>;
-          const SR row = static_cast<const SR*>(keys)[i];
+          const SR row = (static_cast<const SR*>(keys) + b0)[rel];
           if constexpr (SR::KW == 2) b.k[r] = (KT)(((uint64_t)row.w[1] << 32) | row.w[0]);
           else b.k[r] = (KT)(int32_t)row.w[0];
           if constexpr (VD == AGG_F32) b.fv[r] = __uint_as_float(row.w[SR::KW]);
           else if constexpr (VD == AGG_I64) b.iv[r] = (int64_t)(((uint64_t)row.w[SR::KW + 1] << 32) | row.w[SR::KW]);
           else b.iv[r] = (int32_t)row.w[SR::KW];
         } else {
-          b.k[r] = (KT)load_key<KD>(keys, i);
+          b.k[r] = (static_cast<const KT*>(keys) + b0)[rel];
           if constexpr (G != G_COUNT) {
-            if constexpr (VD == AGG_F32) b.fv[r] = static_cast<const float*>(vals)[i];
-            else b.iv[r] = (IVT)load_ival<VD>(vals, i);
+            if constexpr (VD == AGG_F32) b.fv[r] = (static_cast<const float*>(vals) + b0)[rel];
+            else b.iv[r] = (static_cast<const IVT*>(vals) + b0)[rel];
           }
         }
       }
     };
     auto fold = [&](Batch& b, int64_t base) {
+      // rows of this batch that exist: r * step < last - base
+      const uint32_t left = (uint32_t)std::max<int64_t>(0, std::min<int64_t>(last - base, (int64_t)R * step));
       // the batch's loads are complete before its first row is folded: left
       // alone, the compiler sinks a value load into the branch that uses it,
       // and that load's whole latency then stalls the wave
@@ -648,7 +650,7 @@ struct LdsTable {
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (base + r * step >= last) break;
+        if ((uint32_t)r * step32 >= left) break;
         const KT k = b.k[r];
         const uint64_t hk = REP > 1 ? few_hash<KD>(k) : key_hash<KD>((int64_t)k);
         if (SUB && ((uint32_t)(hk >> sub_shift) & sub_mask) != sub) continue;  // another pass's row
